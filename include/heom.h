@@ -1,0 +1,208 @@
+/*
+ * heom.h -- C ABI of libheom: symmetry-adapted HEOM for the permutationally
+ * invariant Holstein-Tavis-Cummings model on AMD Instinct MI355X (gfx950).
+ *
+ * Method: Mondal & Huo, "Symmetry Adapted Hierarchical Equations of Motion
+ * for Exact Simulations of Large Polariton Systems" (arXiv 2608.20657).
+ * The library propagates the unique complex variables Z, X_q, Y_q, P_q,
+ * S_{q,r}, T_q (Sec. V.A) of every canonical occupation pattern (Sec. IV)
+ * with the matrix-free right-hand side of Sec. V.C and classical RK4.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Return value: HEOM_OK (0) or a negative HEOM_E_* code; the message of the
+ *   last failure on the calling thread is heom_last_error(). No entry point
+ *   aborts or throws. Asynchronous device errors surface at the next call that
+ *   synchronizes or checks the stream.
+ * - Pointers named *_dev are device memory owned by the caller (for example
+ *   torch tensors); the library never allocates device memory itself. Host
+ *   pointers are caller-owned and only read during the call unless stated.
+ * - `stream` is a hipStream_t passed as void* (NULL = the null stream). All
+ *   device work is enqueued on it; calls return before it completes.
+ * - Complex numbers are interleaved (re, im) doubles (torch complex128) or
+ *   floats (complex64).
+ * - State vector layout (Eq. global-R): one block per canonical pattern, in
+ *   the library's pattern order (tier ascending; within a tier the
+ *   distinguished molecules' local vectors, smaller first, then the pool
+ *   vectors compared entry by entry, larger first; local vectors are ordered
+ *   by (|v|, v_0, .., v_{m-1})). A block is the (G+1)x(G+1) category matrix
+ *   row-major with index 0 = cavity -- Z at (0,0), Y_q at (0,q), X_q at
+ *   (q,0), P_q at (q,q), S_{q,r} at (q,r) -- followed by T_q for each
+ *   category with M_q >= 2. Categories: the d distinguished molecules, the
+ *   distinct nonzero pool vectors in pattern order, then the zero pool vector
+ *   if present. Block length (G+1)^2 + h (Eq. uvar-count).
+ */
+#ifndef HEOM_H
+#define HEOM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define HEOM_OK             0
+#define HEOM_E_INVAL       -1   /* invalid argument */
+#define HEOM_E_NOMEM       -2   /* host allocation failed */
+#define HEOM_E_TOO_LARGE   -3   /* structure or buffer exceeds a stated limit */
+#define HEOM_E_HIP         -4   /* a HIP runtime call failed */
+#define HEOM_E_NONFINITE   -5   /* a non-finite observable was detected */
+#define HEOM_E_UNSUPPORTED -6   /* outside the implemented parameter range */
+#define HEOM_E_STATE       -7   /* call order violated (e.g. not uploaded) */
+
+#define HEOM_MAX_M   8     /* exponentials per bath */
+#define HEOM_MAX_L   63    /* hierarchy depth */
+#define HEOM_MAX_G   16    /* categories per pattern */
+#define HEOM_NOBS    10    /* observables per sample, see heom_observables */
+
+#define HEOM_FP64    0     /* precision: complex FP64 throughout */
+#define HEOM_FP32    1     /* precision: complex FP32 RK4 increments, FP64 state */
+
+/* One problem (Sec. II, Eqs. HS, BCF-exp, scaled-HEOM; Sec. VI.B for d).
+ * Units are the caller's, with hbar = 1. */
+typedef struct heom_problem {
+    int64_t N;               /* molecules, >= 1 (Eq. basis) */
+    int32_t m;               /* exponentials per local bath, 1..HEOM_MAX_M (Eq. BCF-exp) */
+    int32_t L;               /* hierarchy depth, 0..HEOM_MAX_L (hard cutoff, Sec. II.C) */
+    int32_t d;               /* distinguished molecules 1..d kept explicit, 0 <= d <= N (Eq. N-symmetric-pool) */
+    int32_t reserved;        /* must be 0 */
+    const double *c;         /* 2m doubles: (re, im) of c_k (Eq. BCF-exp) */
+    const double *c_check;   /* 2m doubles: c_check_k, or NULL for conj(c_k) (real rates) */
+    const double *nu;        /* m real decay rates nu_k >= 0 (Eq. tier-damping) */
+    double eps;              /* molecular transition energy (Eq. HS) */
+    double omega_c;          /* cavity frequency (Eq. HS) */
+    double g;                /* single-molecule coupling (Eq. HS) */
+    double kappa;            /* cavity loss rate: -(kappa/2){|c><c|, .} on every ADO */
+    double terminator;       /* Ishizaki-Tanimura Delta: -Delta sum_i [Q_i,[Q_i, .]] (0 = off) */
+} heom_problem;
+
+typedef struct heom_tables heom_tables;   /* opaque host handle */
+
+typedef struct heom_sizes {
+    int64_t n_patterns;      /* canonical patterns (Eq. canonical-count-one for m = 1) */
+    int64_t n_var;           /* unique variables = state vector length (Eq. Du-one) */
+    int64_t n_conn;          /* connection records (one per pattern, category, channel, direction) */
+    int64_t n_tiles;         /* workgroup tiles of whole patterns */
+    int64_t n_categories;    /* sum of G over patterns */
+    int64_t table_bytes;     /* device bytes heom_upload needs */
+    int64_t work_bytes_fp64; /* device work bytes heom_propagate needs at HEOM_FP64 */
+    int64_t work_bytes_fp32; /* device work bytes heom_propagate needs at HEOM_FP32 */
+    int64_t tier0_size;      /* unique variables of the empty pattern */
+    int32_t max_G;           /* largest category count */
+    int32_t tile_vars;       /* variables per tile (workgroup size) */
+    int64_t hier_gathers;    /* hierarchy reads of one right-hand side */
+} heom_sizes;
+
+/* Build the pattern list, unique-variable layout and connection tables of
+ * Sec. IV-V on the host (the precomputation of Sec. V.C.4). Reads `prob` and
+ * its arrays during the call only. On success *out owns a new handle (free
+ * with heom_free_tables). Errors: E_INVAL for out-of-range arguments,
+ * E_UNSUPPORTED if a pattern has more than HEOM_MAX_G categories, E_TOO_LARGE
+ * if the state exceeds 2^32-1 variables, E_NOMEM. No device call is made. */
+int heom_build_tables(const heom_problem *prob, heom_tables **out);
+
+/* Change the numeric parameters (c, c_check, nu, eps, omega_c, g, kappa,
+ * terminator, and N when the structure is unchanged) of built tables. The
+ * structure key (min(N, L+d+2), m, L, d) must be unchanged: beyond
+ * saturation N enters only through M_0 (Sec. V.C.4). Takes effect at the next
+ * heom_upload. Errors: E_INVAL if the structure would change. */
+int heom_set_params(heom_tables *t, const heom_problem *prob);
+
+/* Sizes of built tables (host only). */
+int heom_table_info(const heom_tables *t, heom_sizes *out);
+
+/* Copy the device image of the tables (pattern headers, categories,
+ * connection records, tiles, coefficient look-up tables) into caller device
+ * memory `dev` of `bytes` >= table_bytes, 256-byte aligned, on `stream`. The
+ * handle remembers `dev`; the caller keeps it alive and unchanged while the
+ * handle is used. The host staging copy stays owned by the handle. */
+int heom_upload(heom_tables *t, void *dev, size_t bytes, void *stream);
+
+/* Tier-0 unique variables of the pure initial state
+ *   |psi> = a_c |c> + sum_{j<d} a_dist[j] |e_{j+1}> + a_pool sum_{pool i} |e_i>,
+ * rho_S(0) = |psi><psi|, which is invariant under every relabeling of the
+ * pool (Eqs. symmetric-initial-density, localized-residual-symmetry). This
+ * covers the photon, bright, upper/lower polariton states (Eqs.
+ * cavity-initial-uvar ... lower-polariton-initial), a localized excitation
+ * and the cavity-site superposition of Sec. VII. Amplitudes are complex
+ * (re, im) pairs; a_dist has 2d doubles (may be NULL if d = 0).
+ * out: 2*tier0_size doubles (host). Mixtures follow by linearity. */
+int heom_tier0_pure(const heom_tables *t, const double a_c[2], const double *a_dist,
+                    const double a_pool[2], double *out);
+
+/* Factorized initial condition (Eqs. factorized-initial-zero/-higher):
+ * y_dev (n_var complex128) gets the tier-0 variables `tier0` (host,
+ * 2*tier0_size doubles) and zeros elsewhere. Requires heom_upload. */
+int heom_init_state(const heom_tables *t, const double *tier0, void *y_dev, void *stream);
+
+/* One matrix-free right-hand side dy = M_u y (Eq. uvar-propagator), complex
+ * FP64: the commutator with H_S through grouped multiplicity sums
+ * (Eqs. grouped-row-sum, grouped-column-sum, HZ, HX), -Gamma_Lambda damping
+ * (Eq. Gamma-Lambda-one and its m-channel form), cavity loss, the terminator
+ * if set, and the hierarchy couplings read through the connection records
+ * (Eqs. uvar-up, uvar-down). y_dev and dy_dev: n_var complex128, distinct.
+ * Requires heom_upload. */
+int heom_rhs(const heom_tables *t, const void *y_dev, void *dy_dev, void *stream);
+
+/* Propagate y_dev in place by nsteps classical RK4 steps of size dt (the
+ * integrator of Sec. VII.C). The linear generator is autonomous, so a step
+ * is evaluated as y + h M (y + h/2 M (y + h/3 M (y + h/4 M y))), the same
+ * degree-4 polynomial in hM as the k1..k4 form, with four fused
+ * right-hand-side + combination stages.
+ *   precision HEOM_FP64: all stages in complex FP64; work_dev holds
+ *     work_bytes_fp64 bytes (two state vectors).
+ *   precision HEOM_FP32: y stays complex FP64; the stage increments are
+ *     stored and gathered as complex FP32 while multiplicities, square-root
+ *     weights, damping and the combination with y stay FP64;
+ *     work_dev holds work_bytes_fp32 bytes.
+ * If obs_every > 0, obs_dev (device, (nsteps/obs_every + 1)*HEOM_NOBS
+ * doubles) receives the observables of heom_observables before the first
+ * step and after every obs_every steps. obs_dev may be NULL if obs_every is 0.
+ * Requires heom_upload. */
+int heom_propagate(const heom_tables *t, void *y_dev, void *work_dev, size_t work_bytes,
+                   double dt, int64_t nsteps, int64_t obs_every, double *obs_dev,
+                   int precision, void *stream);
+
+/* Observables of the physical reduced density operator, the tier-0 block
+ * (Sec. V.D, generalized to d distinguished molecules by grouping each
+ * category with its multiplicity). obs_dev receives HEOM_NOBS doubles:
+ *   0 Tr rho_S (real part)   1 P_cav = Z        2 P_exc = sum_q M_q P_q
+ *   3 P_B                    4 P_D = P_exc - P_B
+ *   5 P_+                    6 P_-  (Eq. polariton-states, theta = atan2(2 g sqrt N, omega_c - eps)/2)
+ *   7 population of molecule 1   8 population of molecules 2..N   9 Im Tr rho_S
+ * (Eqs. trace-uvar, Pcav-uvar, Pexc-uvar, PB-uvar, PD-uvar, Pplus-uvar,
+ * Pminus-uvar). Requires heom_upload. */
+int heom_observables(const heom_tables *t, const void *y_dev, double *obs_dev, void *stream);
+
+/* Serialized canonical form of the tables, for bit-exact comparison on the
+ * host. Writes int64 values to `out` (capacity `cap` entries, may be NULL to
+ * query) and the required count to *needed:
+ *   [n_patterns, n_var, m, d]
+ *   per pattern: [offset, G, tier] then per category [dist label or -1,
+ *     multiplicity, v_0 .. v_{m-1}]
+ *   then per pattern, per category q, per channel k, up (if tier < L) then
+ *   down (if v_k(q) > 0): [target pattern, q', r'_0 .. r'_{G-1}] where q' is
+ *   the moved molecule's category in the target and r'_r the category of
+ *   the unmoved members of source category r (-1 if none remain). */
+int heom_export_layout(const heom_tables *t, int64_t *out, size_t cap, size_t *needed);
+
+/* Coefficient look-up tables as used by the kernels (host copy):
+ * out[k*(L+1) + n] = sqrt((n+1)|c_k|) (up, n = 0..L) followed by
+ * out[m*(L+1) + k*(L+1) + n] = sqrt(n/|c_k|) (down, n = 0..L); zero for a
+ * channel with c_k = 0. Capacity cap doubles; *needed = 2m(L+1). */
+int heom_export_coefficients(const heom_tables *t, double *out, size_t cap, size_t *needed);
+
+/* Release a handle (NULL is allowed). Device memory is the caller's. */
+void heom_free_tables(heom_tables *t);
+
+/* Message of the last failure on this thread ("" if none). */
+const char *heom_last_error(void);
+
+/* Library version string. */
+const char *heom_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HEOM_H */

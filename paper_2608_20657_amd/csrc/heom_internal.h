@@ -1,0 +1,129 @@
+// Internal definitions shared by the host table builder (tables.cpp) and the
+// gfx950 kernels (device.hip): the device image of the tables and the
+// category remap rule of a connection record.
+#pragma once
+
+#include <cstdint>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "heom.h"
+
+#ifdef __HIPCC__
+#define HEOM_HD __host__ __device__ __forceinline__
+#else
+#define HEOM_HD inline
+#endif
+
+namespace heom {
+
+// One canonical pattern (Sec. IV.A). 32 bytes.
+struct PatHdr {
+    uint32_t off;        // first unique variable of the block
+    uint32_t cat_base;   // index of the first CatRec of the pattern
+    uint32_t conn_base;  // index of the first Conn of the pattern
+    uint16_t tmask;      // bit q: category q has M_q >= 2 and owns a T_q
+    uint8_t  G;          // number of categories
+    uint8_t  tier;       // |Lambda|
+    uint64_t cnt;        // byte k: sum over molecules of n_ik (for Gamma_Lambda)
+    uint32_t r;          // nonzero pool molecules; M_0 = (N - d) - r
+    uint32_t size;       // (G+1)^2 + h
+};
+static_assert(sizeof(PatHdr) == 32, "PatHdr layout");
+
+enum : uint16_t { CAT_ZERO = 1, CAT_DIST = 2 };
+
+// One occupation category of a pattern (Sec. V.A). 16 bytes.
+struct CatRec {
+    uint64_t vec;        // byte k: component k of the local vector
+    uint32_t mult;       // M_q (0 for the zero category: its M_0 is per instance)
+    uint16_t conn_off;   // first Conn of this category, relative to conn_base
+    uint16_t flags;      // CAT_ZERO, CAT_DIST
+};
+static_assert(sizeof(CatRec) == 16, "CatRec layout");
+
+// One connection: moving one molecule of a category by +-e_k
+// (Eqs. raw-target-*, canonical-target-*). 8 bytes.
+//   info bits 0-4   G' of the target
+//        bits 5-8   q', category of the moved molecule in the target
+//        bit  9     the source category vanishes (its only molecule moved)
+//        bit  10    q' is a category the source did not have
+//        bits 16-31 tmask of the target
+// Records of a category: the m up moves (if tier < L) then the down moves of
+// the channels with v_k > 0, in channel order.
+struct Conn {
+    uint32_t off;
+    uint32_t info;
+};
+static_assert(sizeof(Conn) == 8, "Conn layout");
+
+HEOM_HD uint32_t conn_G(uint32_t info) { return info & 31u; }
+HEOM_HD uint32_t conn_q(uint32_t info) { return (info >> 5) & 15u; }
+HEOM_HD bool conn_vanish(uint32_t info) { return (info >> 9) & 1u; }
+HEOM_HD bool conn_new(uint32_t info) { return (info >> 10) & 1u; }
+HEOM_HD uint32_t conn_tmask(uint32_t info) { return info >> 16; }
+
+// Category in the target of the unmoved molecules of source category r, for
+// a move of one molecule of source category q. Unmoved categories keep their
+// vectors and relative order; the target list is the source list without q
+// (if it vanished) with q' inserted (if new).
+HEOM_HD int conn_remap(uint32_t info, int q, int r) {
+    int r1 = r - ((conn_vanish(info) && r > q) ? 1 : 0);
+    return r1 + ((conn_new(info) && r1 >= (int)conn_q(info)) ? 1 : 0);
+}
+
+// Per-instance numeric parameters (device image header). 256-byte aligned.
+struct InstParams {
+    double g;          // single-molecule coupling
+    double delta;      // eps - omega_c
+    double kappa;      // cavity loss rate
+    double term;       // terminator Delta
+    double npool;      // N - d as double
+    double Nd;         // N as double
+    double inv_sqrtN;  // 1/sqrt(N)
+    double cos_th, sin_th;  // polariton mixing angle (Eq. polariton-states)
+    double nu[HEOM_MAX_M];
+    double cr[HEOM_MAX_M], ci[HEOM_MAX_M];      // c_k
+    double ccr[HEOM_MAX_M], cci[HEOM_MAX_M];    // c_check_k
+    int32_t m, L, d, n_pat;
+    uint32_t n_var, n_tiles, tile_vars, pad;
+    // byte offsets of the sections from the image base
+    uint64_t off_lut, off_hdr, off_cat, off_conn, off_tile;
+};
+
+struct HostTables {
+    heom_problem prob;                 // copy (array pointers cleared)
+    std::vector<double> c, cc, nu;
+    int m = 0, L = 0, d = 0;
+    int64_t N = 0;
+    int32_t tile_vars = 256;
+    // local vectors, nonzero, descending; id nv = zero vector
+    std::vector<uint64_t> vecs;
+    // patterns
+    std::vector<PatHdr> hdr;
+    std::vector<CatRec> cat;
+    std::vector<Conn> conn;
+    std::vector<uint32_t> conn_target;  // target pattern index per Conn
+    std::vector<uint32_t> tiles;        // first pattern of each tile, then n_pat
+    std::vector<uint16_t> pat_ids;      // flat: d dist ids + pool ids
+    std::vector<uint32_t> pat_start;    // per pattern start in pat_ids, then end
+    uint32_t n_var = 0;
+    int max_G = 0;
+    int64_t hier_gathers = 0;
+    std::vector<double> lut;            // up[k][n] then dn[k][n]
+    std::vector<unsigned char> image;   // device image (host staging)
+    void *dev = nullptr;                // uploaded image
+    size_t dev_bytes = 0;
+    bool uploaded = false;
+};
+
+// host-side helpers implemented in tables.cpp
+int build(const heom_problem *p, HostTables *t, std::string *err);
+int set_params(HostTables *t, const heom_problem *p, std::string *err);
+void pack_image(HostTables *t);
+size_t tier0_size(const HostTables &t);
+
+inline uint32_t vcomp(uint64_t v, int k) { return (uint32_t)((v >> (8 * k)) & 0xffu); }
+
+}  // namespace heom

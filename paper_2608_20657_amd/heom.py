@@ -1,0 +1,210 @@
+"""Python binding of libheom (include/heom.h): argument marshalling only.
+
+Every step of the hot path runs in the library's HIP kernels; this module
+converts Python values to the C structs, passes device pointers of torch
+tensors (torch is used for device memory and streams only), and turns error
+codes into exceptions. Importing it loads libheom.so and fails loudly if the
+library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libheom.so")
+
+HEOM_OK = 0
+HEOM_NOBS = 10
+HEOM_FP64 = 0
+HEOM_FP32 = 1
+ERRORS = {-1: "E_INVAL", -2: "E_NOMEM", -3: "E_TOO_LARGE", -4: "E_HIP", -5: "E_NONFINITE",
+          -6: "E_UNSUPPORTED", -7: "E_STATE"}
+
+# every symbol include/heom.h declares
+SYMBOLS = ["heom_build_tables", "heom_set_params", "heom_table_info", "heom_upload", "heom_tier0_pure",
+           "heom_init_state", "heom_rhs", "heom_propagate", "heom_observables", "heom_export_layout",
+           "heom_export_coefficients", "heom_free_tables", "heom_last_error", "heom_version"]
+
+
+class HeomError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class _Problem(ctypes.Structure):
+    _fields_ = [("N", ctypes.c_int64), ("m", ctypes.c_int32), ("L", ctypes.c_int32),
+                ("d", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("c", ctypes.POINTER(ctypes.c_double)), ("c_check", ctypes.POINTER(ctypes.c_double)),
+                ("nu", ctypes.POINTER(ctypes.c_double)),
+                ("eps", ctypes.c_double), ("omega_c", ctypes.c_double), ("g", ctypes.c_double),
+                ("kappa", ctypes.c_double), ("terminator", ctypes.c_double)]
+
+
+class _Sizes(ctypes.Structure):
+    _fields_ = [("n_patterns", ctypes.c_int64), ("n_var", ctypes.c_int64), ("n_conn", ctypes.c_int64),
+                ("n_tiles", ctypes.c_int64), ("n_categories", ctypes.c_int64),
+                ("table_bytes", ctypes.c_int64), ("work_bytes_fp64", ctypes.c_int64),
+                ("work_bytes_fp32", ctypes.c_int64), ("tier0_size", ctypes.c_int64),
+                ("max_G", ctypes.c_int32), ("tile_vars", ctypes.c_int32), ("hier_gathers", ctypes.c_int64)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                          "or python paper_2608_20657_amd/build.py")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i64, dp = ctypes.c_void_p, ctypes.c_int64, ctypes.POINTER(ctypes.c_double)
+    sig = {
+        "heom_build_tables": [ctypes.POINTER(_Problem), ctypes.POINTER(vp)],
+        "heom_set_params": [vp, ctypes.POINTER(_Problem)],
+        "heom_table_info": [vp, ctypes.POINTER(_Sizes)],
+        "heom_upload": [vp, vp, ctypes.c_size_t, vp],
+        "heom_tier0_pure": [vp, dp, dp, dp, dp],
+        "heom_init_state": [vp, dp, vp, vp],
+        "heom_rhs": [vp, vp, vp, vp],
+        "heom_propagate": [vp, vp, vp, ctypes.c_size_t, ctypes.c_double, i64, i64, vp, ctypes.c_int, vp],
+        "heom_observables": [vp, vp, vp, vp],
+        "heom_export_layout": [vp, ctypes.POINTER(i64), ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)],
+        "heom_export_coefficients": [vp, dp, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)],
+    }
+    for name, args in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = ctypes.c_int
+    lib.heom_free_tables.argtypes = [vp]
+    lib.heom_free_tables.restype = None
+    lib.heom_last_error.restype = ctypes.c_char_p
+    lib.heom_version.restype = ctypes.c_char_p
+    return lib
+
+
+LIB = _load()
+
+
+def _check(rc: int):
+    if rc != HEOM_OK:
+        raise HeomError(rc, LIB.heom_last_error().decode())
+
+
+def _dbl(values: Sequence[float]):
+    arr = (ctypes.c_double * len(values))(*values)
+    return arr
+
+
+def _problem_struct(p):
+    c = _dbl([x for z in p.c for x in (complex(z).real, complex(z).imag)])
+    cc = _dbl([x for z in p.c_check for x in (complex(z).real, complex(z).imag)])
+    nu = _dbl([float(x) for x in p.nu])
+    s = _Problem(N=int(p.N), m=int(p.m), L=int(p.L), d=int(p.d), reserved=0,
+                 c=ctypes.cast(c, ctypes.POINTER(ctypes.c_double)),
+                 c_check=ctypes.cast(cc, ctypes.POINTER(ctypes.c_double)),
+                 nu=ctypes.cast(nu, ctypes.POINTER(ctypes.c_double)),
+                 eps=float(p.eps), omega_c=float(p.omega_c), g=float(p.g),
+                 kappa=float(p.kappa), terminator=float(p.terminator))
+    return s, (c, cc, nu)
+
+
+def _ptr(t) -> int:
+    """Device (or host) address of a torch tensor or numpy array."""
+    if hasattr(t, "data_ptr"):
+        return t.data_ptr()
+    return t.ctypes.data
+
+
+def _stream(stream) -> Optional[int]:
+    if stream is None:
+        return None
+    if hasattr(stream, "cuda_stream"):
+        return stream.cuda_stream
+    return int(stream)
+
+
+class Tables:
+    """Owner of one heom_tables handle."""
+
+    def __init__(self, problem):
+        self.problem = problem
+        s, keep = _problem_struct(problem)
+        h = ctypes.c_void_p()
+        _check(LIB.heom_build_tables(ctypes.byref(s), ctypes.byref(h)))
+        self._h = h
+        self.image = None   # device buffer once uploaded
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            LIB.heom_free_tables(h)
+            self._h = None
+
+    @property
+    def handle(self):
+        return self._h
+
+    def info(self) -> dict:
+        z = _Sizes()
+        _check(LIB.heom_table_info(self._h, ctypes.byref(z)))
+        return {name: getattr(z, name) for name, _ in _Sizes._fields_}
+
+    def set_params(self, problem):
+        s, keep = _problem_struct(problem)
+        _check(LIB.heom_set_params(self._h, ctypes.byref(s)))
+        self.problem = problem
+
+    def upload(self, device_buffer, stream=None):
+        """Copy the table image into a caller-owned device buffer (a uint8
+        torch tensor of at least info()['table_bytes'] bytes)."""
+        nbytes = device_buffer.numel() * device_buffer.element_size()
+        _check(LIB.heom_upload(self._h, _ptr(device_buffer), nbytes, _stream(stream)))
+        self.image = device_buffer
+
+    def tier0_pure(self, a_c: complex, a_pool: complex, a_dist: Sequence[complex] = ()) -> np.ndarray:
+        n0 = self.info()["tier0_size"]
+        out = np.zeros(2 * n0)
+        ac = _dbl([complex(a_c).real, complex(a_c).imag])
+        ap = _dbl([complex(a_pool).real, complex(a_pool).imag])
+        ad = _dbl([x for z in a_dist for x in (complex(z).real, complex(z).imag)]) if len(a_dist) else None
+        _check(LIB.heom_tier0_pure(self._h, ac, ad, ap, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        return out.view(np.complex128)
+
+    def init_state(self, tier0: np.ndarray, y, stream=None):
+        t0 = np.ascontiguousarray(np.asarray(tier0, dtype=np.complex128)).view(np.float64)
+        _check(LIB.heom_init_state(self._h, t0.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), _ptr(y),
+                                   _stream(stream)))
+
+    def rhs(self, y, dy, stream=None):
+        _check(LIB.heom_rhs(self._h, _ptr(y), _ptr(dy), _stream(stream)))
+
+    def propagate(self, y, work, dt: float, nsteps: int, obs_every: int = 0, obs=None,
+                  precision: int = HEOM_FP64, stream=None):
+        wbytes = work.numel() * work.element_size()
+        _check(LIB.heom_propagate(self._h, _ptr(y), _ptr(work), wbytes, float(dt), int(nsteps),
+                                  int(obs_every), _ptr(obs) if obs is not None else None,
+                                  int(precision), _stream(stream)))
+
+    def observables(self, y, obs, stream=None):
+        _check(LIB.heom_observables(self._h, _ptr(y), _ptr(obs), _stream(stream)))
+
+    def export_layout(self) -> np.ndarray:
+        need = ctypes.c_size_t()
+        _check(LIB.heom_export_layout(self._h, None, 0, ctypes.byref(need)))
+        out = np.zeros(need.value, dtype=np.int64)
+        _check(LIB.heom_export_layout(self._h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                      need.value, ctypes.byref(need)))
+        return out
+
+    def export_coefficients(self) -> np.ndarray:
+        need = ctypes.c_size_t()
+        _check(LIB.heom_export_coefficients(self._h, None, 0, ctypes.byref(need)))
+        out = np.zeros(need.value)
+        _check(LIB.heom_export_coefficients(self._h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                            need.value, ctypes.byref(need)))
+        return out
+
+
+def version() -> str:
+    return LIB.heom_version().decode()

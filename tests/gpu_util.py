@@ -1,0 +1,62 @@
+"""Helpers for the GPU tests: device memory through torch, calls through the
+C ABI binding."""
+import math
+
+import numpy as np
+
+
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        import pytest
+        pytest.skip("no GPU")
+    return torch
+
+
+def upload(p):
+    """Build tables for problem p and upload them; returns (tables, torch)."""
+    torch = torch_cuda()
+    from paper_2608_20657_amd import heom
+    T = heom.Tables(p)
+    info = T.info()
+    buf = torch.empty(info["table_bytes"], dtype=torch.uint8, device="cuda")
+    T.upload(buf, torch.cuda.current_stream())
+    return T, torch
+
+
+def gpu_rhs(T, torch, y: np.ndarray) -> np.ndarray:
+    yd = torch.from_numpy(np.ascontiguousarray(y)).to("cuda")
+    dy = torch.empty_like(yd)
+    T.rhs(yd, dy, torch.cuda.current_stream())
+    torch.cuda.synchronize()
+    return dy.cpu().numpy()
+
+
+def gpu_propagate(T, torch, tier0: np.ndarray, dt: float, steps: int, every: int, precision: int = 0):
+    info = T.info()
+    s = torch.cuda.current_stream()
+    y = torch.empty(info["n_var"], dtype=torch.complex128, device="cuda")
+    T.init_state(tier0, y, s)
+    wbytes = info["work_bytes_fp64"] if precision == 0 else info["work_bytes_fp32"]
+    work = torch.empty(wbytes, dtype=torch.uint8, device="cuda")
+    nobs = steps // every + 1 if every > 0 else 0
+    obs = torch.zeros(max(nobs, 1) * 10, dtype=torch.float64, device="cuda")
+    T.propagate(y, work, dt, steps, every, obs if every > 0 else None, precision, s)
+    torch.cuda.synchronize()
+    return y.cpu().numpy(), obs.cpu().numpy().reshape(-1, 10)[:nobs]
+
+
+def rhs_bound(A, y: np.ndarray, c: float = 1e-13) -> np.ndarray:
+    """Elementwise rounding-error scale of A @ y: c * (|A| @ |y|)."""
+    return c * (abs(A) @ np.abs(y)) + 1e-300
+
+
+def named_tier0(T, p, state: str) -> np.ndarray:
+    if state == "photon":
+        return T.tier0_pure(1.0, 0.0, [0.0] * p.d)
+    if state == "site1":
+        return T.tier0_pure(0.0, 0.0, [1.0] + [0.0] * (p.d - 1))
+    if state == "upper_polariton":
+        th = 0.5 * math.atan2(2 * p.g * math.sqrt(p.N), p.omega_c - p.eps)
+        return T.tier0_pure(math.cos(th), math.sin(th) / math.sqrt(p.N), [math.sin(th) / math.sqrt(p.N)] * p.d)
+    raise ValueError(state)

@@ -1,0 +1,210 @@
+"""GPU parity of libheom against the CPU oracle, through the C ABI.
+
+* heom_rhs: element by element against the oracle's generator M_u on seeded
+  random vectors, within c * (|M_u| @ |y|) per element (rounding of a sum of
+  a few tens of products), for structures covering d = 0..3, m = 1..8, L = 0,
+  N = 1, switched-off channels, zero rates, detuning, loss, terminator and
+  c_check independent of conj(c); at the largest single-GPU size
+  (N=10^4, m=4, L=10: 17.3 M variables) on sampled rows the oracle computes
+  one by one.
+* heom_propagate (FP64): observables within 1e-10 of max |O| over the
+  trajectory (small workload against the conventional dense HEOM and the
+  unique-variable oracle; localized and saturated workloads against the
+  oracle's stored trajectories).
+* heom_propagate (FP32 increments): populations within 1e-5 absolute.
+* heom_observables, heom_init_state, determinism, nsteps = 0.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+from oracle import conventional, integrate, observables as O, uvar
+from paper_2608_20657_amd import workloads as W
+from tests.gpu_util import gpu_propagate, gpu_rhs, named_tier0, rhs_bound, upload
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+STRUCTS = [(2, 1, 3, 0), (4, 2, 3, 0), (4, 2, 3, 1), (3, 2, 4, 1), (5, 1, 3, 1), (4, 1, 4, 2),
+           (3, 3, 2, 1), (1, 2, 3, 0), (2, 1, 0, 0), (3, 1, 2, 3), (6, 4, 3, 0), (12, 1, 10, 0),
+           (7, 2, 5, 2), (9, 8, 2, 0), (40, 3, 4, 1)]
+
+
+def check_rhs(p, seed=0):
+    T, torch = upload(p)
+    S = uvar.UVarSystem(p)
+    A = S.generator()
+    y = W.random_vector(S.n_var, seed)
+    got = gpu_rhs(T, torch, y)
+    want = A @ y
+    err = np.abs(got - want)
+    bound = rhs_bound(A, y)
+    assert np.all(err <= bound), f"max err {err.max():.3e}, worst ratio {(err / bound).max():.2f}"
+    return T, torch
+
+
+@pytest.mark.parametrize("N,m,L,d", STRUCTS)
+def test_rhs_structures(N, m, L, d):
+    p = W.random_problem(N, m, L, d, seed=3 * N + m + L + d, complex_check=True, terminator=True)
+    check_rhs(p, seed=N)
+
+
+def test_rhs_switched_off_and_static_channels():
+    p = W.random_problem(5, 3, 4, 1, seed=11)
+    p.c[1] = 0j
+    p.c_check[1] = 0j          # channel 1 switched off
+    p.nu[2] = 0.0              # a static (zero-rate) channel
+    check_rhs(p)
+
+
+@pytest.mark.parametrize("name", ["small", "localized", "saturated"])
+def test_rhs_workloads(name):
+    check_rhs(W.WORKLOADS[name](), seed=1)
+
+
+def test_rhs_largest_structure_sampled():
+    p = W.config_roofline_probe()
+    T, torch = upload(p)
+    n = T.info()["n_var"]
+    y = W.random_vector(n, 5)
+    got = gpu_rhs(T, torch, y)
+    S = uvar.UVarSystem(p)
+    assert S.n_var == n
+    rng = np.random.default_rng(7)
+    rows = rng.choice(n, 400, replace=False).tolist() + [0, 1, n - 1] + \
+        [b.offset for b in S.blocks[-3:]] + [S.blocks[1000].offset + 3]
+    ref = S.rows_at(rows)
+    for i in rows:
+        want = sum(c * y[j] for j, c in ref[i].items())
+        scale = sum(abs(c) * abs(y[j]) for j, c in ref[i].items())
+        assert abs(got[i] - want) <= 1e-13 * scale + 1e-300, i
+
+
+def test_rhs_deterministic():
+    p = W.config_localized()
+    T, torch = upload(p)
+    y = W.random_vector(T.info()["n_var"], 2)
+    a = gpu_rhs(T, torch, y)
+    b = gpu_rhs(T, torch, y)
+    assert np.array_equal(a, b)
+
+
+def test_init_and_observables():
+    for (N, d) in [(5, 0), (7, 1), (6, 2)]:
+        p = W.random_problem(N, 2, 2, d, seed=N)
+        T, torch = upload(p)
+        S = uvar.UVarSystem(p)
+        t0 = T.tier0_pure(0.6, 0.8 / math.sqrt(N), [0.1j] * d)
+        y = torch.empty(S.n_var, dtype=torch.complex128, device="cuda")
+        T.init_state(t0, y, torch.cuda.current_stream())
+        yh = y.cpu().numpy()
+        assert np.array_equal(yh[:t0.size], t0) and not np.any(yh[t0.size:])
+        # observables of a random Hermitian tier-0 block
+        rng = np.random.default_rng(N)
+        labs = conventional.labels(N, 2, 2)
+        full = S.expand(rng.standard_normal(S.n_var) + 1j * rng.standard_normal(S.n_var), labs)
+        D = N + 1
+        rho = full[:D * D].reshape(D, D)
+        rho = rho + rho.conj().T
+        u = S.compress(np.r_[rho.reshape(-1), np.zeros((len(labs) - 1) * D * D)], labs)
+        ob = torch.zeros(10, dtype=torch.float64, device="cuda")
+        T.observables(torch.from_numpy(u).cuda(), ob, torch.cuda.current_stream())
+        torch.cuda.synchronize()
+        want = O.from_tier0(S, u)
+        assert np.abs(ob.cpu().numpy() - want).max() <= 1e-13 * np.abs(want).max()
+
+
+def test_propagate_small_vs_conventional():
+    p = W.config_small()
+    T, torch = upload(p)
+    dt, steps, every = 0.05, 2000, 20
+    _, obs = gpu_propagate(T, torch, named_tier0(T, p, "photon"), dt, steps, every)
+    A, labs = conventional.generator(p)
+    D = p.N + 1
+    rho0 = np.zeros((D, D), complex)
+    rho0[0, 0] = 1
+    _, oc = integrate.propagate(A, conventional.initial_vector(rho0, len(labs)), dt, steps, every,
+                                observe=lambda y: O.dense(y[:D * D].reshape(D, D), p.N, p.eps, p.omega_c, p.g))
+    oc = np.array(oc)
+    for j in range(9):
+        assert np.abs(obs[:, j] - oc[:, j]).max() <= 1e-10 * max(np.abs(oc[:, j]).max(), 1e-300), j
+    assert abs(obs[0, 1] - 1.0) < 1e-15
+
+
+def test_propagate_short_vs_oracle_all_states():
+    # trajectory of the unique-variable oracle, several states and structures
+    for (N, m, L, d, state) in [(6, 2, 3, 1, "site1"), (9, 1, 5, 0, "upper_polariton"), (5, 3, 2, 2, "photon")]:
+        p = W.random_problem(N, m, L, d, seed=N, loss=True)
+        T, torch = upload(p)
+        t0 = named_tier0(T, p, state)
+        S = uvar.UVarSystem(p)
+        y0 = np.zeros(S.n_var, complex)
+        y0[:t0.size] = t0
+        _, oo = integrate.propagate(S.generator(), y0, 0.02, 300, 10, observe=lambda y: O.from_tier0(S, y))
+        oo = np.array(oo)
+        yg, og = gpu_propagate(T, torch, t0, 0.02, 300, 10)
+        for j in range(9):
+            assert np.abs(og[:, j] - oo[:, j]).max() <= 1e-10 * max(np.abs(oo[:, j]).max(), 1e-300)
+
+
+def _golden(name):
+    path = os.path.join(GOLDEN, f"traj_{name}.json")
+    if not os.path.exists(path):
+        pytest.skip(f"{path} missing")
+    return json.load(open(path))
+
+
+@pytest.mark.parametrize("name", ["localized", "saturated"])
+def test_propagate_fp64_vs_golden(name):
+    g = _golden(name)
+    p = W.WORKLOADS[name]()
+    T, torch = upload(p)
+    _, obs = gpu_propagate(T, torch, named_tier0(T, p, g["state"]), g["dt"], g["steps"], g["every"])
+    ref = np.array(g["observables"])
+    assert obs.shape == ref.shape
+    for j in range(9):
+        assert np.abs(obs[:, j] - ref[:, j]).max() <= 1e-10 * max(np.abs(ref[:, j]).max(), 1e-300), j
+
+
+@pytest.mark.parametrize("name", ["localized", "saturated"])
+def test_propagate_fp32_vs_golden(name):
+    g = _golden(name)
+    p = W.WORKLOADS[name]()
+    T, torch = upload(p)
+    _, obs = gpu_propagate(T, torch, named_tier0(T, p, g["state"]), g["dt"], g["steps"], g["every"], precision=1)
+    ref = np.array(g["observables"])
+    err = np.abs(obs[:, 1:9] - ref[:, 1:9]).max()
+    assert err <= 1e-5, err
+
+
+def test_propagate_fp32_odd_even_steps():
+    p = W.config_localized()
+    T, torch = upload(p)
+    t0 = named_tier0(T, p, "site1")
+    y1, _ = gpu_propagate(T, torch, t0, 0.02, 3, 0, precision=1)
+    y2, _ = gpu_propagate(T, torch, t0, 0.02, 4, 0, precision=1)
+    S = uvar.UVarSystem(p)
+    A = S.generator()
+    y = np.zeros(S.n_var, complex)
+    y[:t0.size] = t0
+    for k, yg in ((3, y1), (4, y2)):
+        yr = y.copy()
+        for _ in range(k):
+            yr = integrate.rk4_step(A, yr, 0.02)
+        assert np.abs(yg - yr).max() < 1e-8
+
+
+def test_propagate_zero_steps_and_determinism():
+    p = W.config_localized()
+    T, torch = upload(p)
+    t0 = named_tier0(T, p, "site1")
+    y0, ob0 = gpu_propagate(T, torch, t0, 0.02, 0, 1)
+    assert np.array_equal(y0[:t0.size], t0) and ob0.shape == (1, 10)
+    assert ob0[0, 7] == 1.0
+    a, oa = gpu_propagate(T, torch, t0, 0.02, 500, 50)
+    b, ob = gpu_propagate(T, torch, t0, 0.02, 500, 50)
+    assert np.array_equal(a, b) and np.array_equal(oa, ob)

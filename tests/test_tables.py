@@ -1,0 +1,140 @@
+"""Host-side checks of libheom (no GPU needed): the library loads and exports
+every symbol of include/heom.h; its tables match the oracle's bit for bit
+(pattern order, categories, multiplicities, offsets, every connection's
+target, moved category and category remap); its coefficient look-up tables
+equal the oracle's coefficient formulas exactly; argument errors come back as
+error codes."""
+import ctypes
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import uvar
+from paper_2608_20657_amd import workloads as W
+from tests.oracle_layout import serialize
+
+heom = pytest.importorskip("paper_2608_20657_amd.heom", reason="libheom.so not built")
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+STRUCTS = [(2, 1, 3, 0), (4, 2, 3, 0), (4, 2, 3, 1), (3, 2, 4, 1), (5, 1, 3, 1), (4, 1, 4, 2),
+           (3, 3, 2, 1), (1, 2, 3, 0), (2, 1, 0, 0), (3, 1, 2, 3), (6, 4, 3, 0), (12, 1, 10, 0),
+           (7, 2, 5, 2), (30, 8, 2, 0)]
+
+
+def test_exports_every_header_symbol():
+    hdr = open(os.path.join(ROOT, "include", "heom.h")).read()
+    declared = sorted(set(re.findall(r"\b(heom_[a-z0-9_]+)\s*\(", hdr)))
+    assert declared, "no declarations found"
+    lib = ctypes.CDLL(heom.LIB_PATH)
+    for name in declared:
+        assert hasattr(lib, name), name
+    assert sorted(heom.SYMBOLS) == declared
+    assert "gfx950" in heom.version()
+
+
+@pytest.mark.parametrize("N,m,L,d", STRUCTS)
+def test_layout_bit_exact(N, m, L, d):
+    p = W.random_problem(N, m, L, d, seed=N + m + L + d, complex_check=True)
+    lib = heom.Tables(p).export_layout()
+    ora = serialize(uvar.UVarSystem(p))
+    assert lib.shape == ora.shape
+    assert np.array_equal(lib, ora)
+
+
+@pytest.mark.parametrize("name", ["small", "localized", "saturated"])
+def test_workload_layouts_bit_exact(name):
+    p = W.WORKLOADS[name]()
+    T = heom.Tables(p)
+    S = uvar.UVarSystem(p)
+    assert np.array_equal(T.export_layout(), serialize(S))
+    info = T.info()
+    assert info["n_patterns"] == len(S.blocks) and info["n_var"] == S.n_var
+    assert info["tier0_size"] == S.blocks[0].size
+
+
+def test_saturated_structure_shared():
+    # beyond N = L + d + 2 only M_0 differs (Sec. V.C.4)
+    p1, p2 = W.config_saturated(), W.config_saturated()
+    p1.N, p2.N = 10, 10 ** 9
+    a, b = heom.Tables(p1).export_layout(), heom.Tables(p2).export_layout()
+    assert a.shape == b.shape
+    diff = np.nonzero(a != b)[0]
+    assert len(diff) > 0
+    # every differing entry is a zero-category multiplicity N - r
+    for i in diff:
+        assert b[i] - a[i] == 10 ** 9 - 10
+
+
+@pytest.mark.parametrize("N,m,L,d", [(3, 2, 4, 1), (12, 1, 10, 0), (5, 3, 3, 0)])
+def test_coefficients_exact(N, m, L, d):
+    p = W.random_problem(N, m, L, d, seed=4)
+    p.c[0] = 0j                                  # a switched-off channel
+    p.c_check[0] = 0j
+    lut = heom.Tables(p).export_coefficients()
+    assert lut.size == 2 * m * (L + 1)
+    for k in range(m):
+        a = abs(complex(p.c[k]))
+        for n in range(L + 1):
+            up = math.sqrt((n + 1) * a) if a else 0.0
+            dn = math.sqrt(n / a) if a else 0.0
+            assert lut[k * (L + 1) + n] == up
+            assert lut[m * (L + 1) + k * (L + 1) + n] == dn
+
+
+def test_tier0_pure_matches_oracle():
+    for (N, d) in [(5, 0), (7, 1), (6, 2), (2, 2)]:
+        p = W.random_problem(N, 1, 2, d, seed=N)
+        T = heom.Tables(p)
+        S = uvar.UVarSystem(p)
+        ac, ap = 0.3 - 0.2j, 0.1 + 0.4j
+        ad = [0.5 + 0.1j, -0.2 + 0.3j][:d]
+
+        def amp(i):
+            if i == 0:
+                return ac
+            return ad[i - 1] if i <= d else ap
+
+        want = S.initial_state(amp=amp)[:S.blocks[0].size]
+        got = T.tier0_pure(ac, ap, ad)
+        assert np.array_equal(got, want)
+
+
+def test_errors():
+    p = W.config_small()
+    bad = W.config_small()
+    bad.m = 0
+    with pytest.raises(heom.HeomError) as e:
+        heom.Tables(bad)
+    assert e.value.code == -1
+    bad = W.config_small()
+    bad.d = 5
+    with pytest.raises(heom.HeomError):
+        heom.Tables(bad)
+    bad = W.config_small()
+    bad.nu = [-1.0]
+    with pytest.raises(heom.HeomError):
+        heom.Tables(bad)
+    T = heom.Tables(p)
+    buf = np.zeros(4, dtype=np.complex128)
+    with pytest.raises(heom.HeomError) as e:
+        T.rhs(buf, np.zeros(4, dtype=np.complex128))   # not uploaded
+    assert e.value.code == -7
+    q = W.config_small()
+    q.N = 7                                           # structure changes (L + d + 2 = 5)
+    with pytest.raises(heom.HeomError):
+        T.set_params(q)
+    q = W.config_small()
+    q.g = 0.5
+    T.set_params(q)                                   # same structure: accepted
+
+
+def test_too_many_categories_rejected():
+    # m = 8, d = 15: sixteen distinguished categories plus the pool
+    p = W.random_problem(40, 1, 1, 15, seed=0)
+    with pytest.raises(heom.HeomError) as e:
+        heom.Tables(p)
+    assert e.value.code == -6
