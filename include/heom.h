@@ -50,6 +50,7 @@ extern "C" {
 #define HEOM_E_NONFINITE   -5   /* a non-finite observable was detected */
 #define HEOM_E_UNSUPPORTED -6   /* outside the implemented parameter range */
 #define HEOM_E_STATE       -7   /* call order violated (e.g. not uploaded) */
+#define HEOM_E_TIMEOUT     -8   /* a grid barrier of the persistent kernel gave up waiting */
 
 #define HEOM_MAX_M   8     /* exponentials per bath */
 #define HEOM_MAX_L   63    /* hierarchy depth */
@@ -192,6 +193,33 @@ int heom_export_layout(const heom_tables *t, int64_t *out, size_t cap, size_t *n
  * out[m*(L+1) + k*(L+1) + n] = sqrt(n/|c_k|) (down, n = 0..L); zero for a
  * channel with c_k = 0. Capacity cap doubles; *needed = 2m(L+1). */
 int heom_export_coefficients(const heom_tables *t, double *out, size_t cap, size_t *needed);
+
+/* Launch configuration of the kernels (the autotuner's knobs). */
+typedef struct heom_tuning {
+    int32_t tile_vars;       /* variables per workgroup tile: 64, 128, 256 or 512 (0 = keep) */
+    int32_t persistent;      /* 1: heom_propagate runs all steps in one cooperative launch with a
+                                grid barrier after each stage; 0: one launch per stage;
+                                2 (default): persistent when the state has at most 256 tiles */
+    int32_t xcd_map;         /* 1: map workgroups to tiles so each XCD streams a contiguous run */
+    int32_t max_workgroups;  /* cap on resident workgroups of the persistent launch (0 = occupancy limit) */
+    int32_t spin_limit;      /* polls before a grid barrier gives up (0 = default, about 4 s) */
+    int32_t cache_policy;    /* streaming (non-temporal) hints: bit 0 own-value loads, bit 1 loads of
+                                the RK4 base vector, bit 2 stores (default 6) */
+} heom_tuning;
+
+/* Set or read the launch configuration. A new tile_vars rebuilds the tiles
+ * and needs a new heom_upload (table_bytes may change). Results do not
+ * depend on the configuration (every variable has one writer, and the sum
+ * order inside a variable is fixed). Errors: E_INVAL if tile_vars is not
+ * allowed or smaller than the largest pattern block. */
+int heom_set_tuning(heom_tables *t, const heom_tuning *tuning);
+int heom_get_tuning(const heom_tables *t, heom_tuning *tuning);
+
+/* Wait for `stream` and report whether the last heom_propagate that used
+ * this work buffer completed: HEOM_OK, or HEOM_E_TIMEOUT if a grid barrier of
+ * the persistent kernel gave up (the state is then invalid). Reads 4 bytes of
+ * work_dev. */
+int heom_work_status(const heom_tables *t, const void *work_dev, size_t work_bytes, void *stream);
 
 /* Release a handle (NULL is allowed). Device memory is the caller's. */
 void heom_free_tables(heom_tables *t);

@@ -46,7 +46,7 @@ struct Dev {
     const PatHdr *hdr;
     const CatRec *cat;
     const Conn *conn;
-    const uint32_t *tiles;
+    const TileRec *tiles;
 };
 
 Dev dev_view(const HostTables &t) {
@@ -58,7 +58,7 @@ Dev dev_view(const HostTables &t) {
     D.hdr = reinterpret_cast<const PatHdr *>(b + ip->off_hdr);
     D.cat = reinterpret_cast<const CatRec *>(b + ip->off_cat);
     D.conn = reinterpret_cast<const Conn *>(b + ip->off_conn);
-    D.tiles = reinterpret_cast<const uint32_t *>(b + ip->off_tile);
+    D.tiles = reinterpret_cast<const TileRec *>(b + ip->off_tile);
     return D;
 }
 
@@ -122,16 +122,6 @@ __device__ __forceinline__ uint32_t tgt_index(Conn cr, int a, int b, bool same) 
 
 __device__ __forceinline__ uint32_t vbyte(uint64_t v, int k) { return (uint32_t)(v >> (8 * k)) & 0xffu; }
 
-// first record of category c for a move in channel k (up or down)
-__device__ __forceinline__ uint32_t rec_up(const PatHdr &H, const CatRec &c, int k) {
-    return H.conn_base + c.conn_off + k;
-}
-__device__ __forceinline__ uint32_t rec_dn(const PatHdr &H, const CatRec &c, int k, bool chi, int m) {
-    uint32_t r = H.conn_base + c.conn_off + (chi ? m : 0);
-    for (int j = 0; j < k; ++j) r += vbyte(c.vec, j) != 0;
-    return r;
-}
-
 // Observables of the tier-0 block v (Sec. V.D, any d).
 __device__ void tier0_observables(const InstParams &P, const PatHdr &H, const CatRec *cats,
                                   const double2 *v, double *out) {
@@ -175,201 +165,429 @@ __device__ void tier0_observables(const InstParams &P, const PatHdr &H, const Ca
 
 constexpr int MAX_TILE = 512;
 
-// One fused stage: out[i] = base(i) + alpha * ((M in)[i] + extra_scale * extra[i])
-// over the variables of one tile per workgroup.
-template <class IN, class OutT, bool BASE_Y, bool BASE_IS_IN, bool EXTRA>
-__global__ __launch_bounds__(MAX_TILE) void stage_kernel(Dev D, IN in, const double2 *ybase,
-                                                       const float2 *extra, double extra_scale,
-                                                       OutT *out, double alpha, double *obs, int xcd) {
-    __shared__ double2 sval[MAX_TILE];
-    __shared__ uint32_t soff[MAX_TILE];
-    const InstParams &P = *D.ip;
-    const uint32_t tile = xcd ? xcd_tile(blockIdx.x, P.n_tiles) : blockIdx.x;
-    const uint32_t p0 = D.tiles[tile], p1 = D.tiles[tile + 1];
-    const uint32_t v0 = D.hdr[p0].off;
-    const uint32_t v1 = (p1 < (uint32_t)P.n_pat) ? D.hdr[p1].off : P.n_var;
-    const uint32_t nloc = v1 - v0, npl = p1 - p0;
-    for (uint32_t i = threadIdx.x; i < nloc; i += blockDim.x) sval[i] = in.load(v0 + i);
-    for (uint32_t j = threadIdx.x; j < npl; j += blockDim.x) soff[j] = D.hdr[p0 + j].off - v0;
-    __syncthreads();
+typedef double dvec2 __attribute__((ext_vector_type(2)));
+typedef float fvec2 __attribute__((ext_vector_type(2)));
 
+__device__ __forceinline__ double2 ld_stream(const double2 *p) {
+    const dvec2 v = __builtin_nontemporal_load(reinterpret_cast<const dvec2 *>(p));
+    return make_double2(v.x, v.y);
+}
+__device__ __forceinline__ void st_stream(double2 *p, double2 v) {
+    dvec2 w = {v.x, v.y};
+    __builtin_nontemporal_store(w, reinterpret_cast<dvec2 *>(p));
+}
+__device__ __forceinline__ void st_stream(float2 *p, double2 v) {
+    fvec2 w = {(float)v.x, (float)v.y};
+    __builtin_nontemporal_store(w, reinterpret_cast<fvec2 *>(p));
+}
+
+// Copy n records of T (a multiple of 8 bytes) from global to LDS, coalesced.
+template <class T>
+__device__ __forceinline__ void stage_copy(T *dst, const T *src, uint32_t n) {
+    static_assert(sizeof(T) % 8 == 0, "record size");
+    const uint2 *s = reinterpret_cast<const uint2 *>(src);
+    uint2 *d = reinterpret_cast<uint2 *>(dst);
+    const uint32_t words = n * (uint32_t)(sizeof(T) / 8);
+    for (uint32_t i = threadIdx.x; i < words; i += blockDim.x) d[i] = s[i];
+}
+
+// Vectors one stage reads and writes:
+//   out[i] = base(i) + alpha * ((M_u in)[i] + extra_scale * extra[i])
+// with in = in64 (+ in32), base = in (BASE 1) or ybase (BASE 2) or 0.
+struct StageArgs {
+    const double2 *in64;
+    const float2 *in32;
+    const double2 *ybase;
+    const float2 *extra;
+    double extra_scale;
+    double2 *out64;
+    float2 *out32;
+    double alpha;
+    double *obs;          // observables of the tier-0 block after this stage
+    uint32_t policy;      // bit 0: non-temporal own-value loads, 1: y loads, 2: stores
+    uint32_t tile0;       // first tile of this launch
+};
+
+enum { BASE_NONE = 0, BASE_IN = 1, BASE_Y = 2 };
+
+// LDS carve-up of one workgroup: tile values, pattern headers, categories,
+// connection records, coefficient tables.
+struct Smem {
+    double2 *val;
+    PatHdr *hdr;
+    CatRec *cat;
+    Conn *con;
+    double *lut;
+};
+
+__device__ __forceinline__ Smem carve(unsigned char *smem, const InstParams &P) {
+    Smem S;
+    S.val = reinterpret_cast<double2 *>(smem);
+    S.hdr = reinterpret_cast<PatHdr *>(smem + 16u * P.tile_vars);
+    S.cat = reinterpret_cast<CatRec *>(S.hdr + P.max_np);
+    S.con = reinterpret_cast<Conn *>(S.cat + P.max_nc);
+    S.lut = reinterpret_cast<double *>(S.con + P.max_nk);
+    return S;
+}
+
+__device__ __forceinline__ void stage_meta(const Dev &D, const TileRec &TR, const Smem &S) {
+    stage_copy(S.hdr, D.hdr + TR.p0, TR.np);
+    stage_copy(S.cat, D.cat + TR.c0, TR.nc);
+    stage_copy(S.con, D.conn + TR.k0, TR.nk);
+}
+
+__device__ __forceinline__ void stage_lut(const Dev &D, const InstParams &P, double *lut) {
+    const uint32_t n = 2u * (uint32_t)P.m * (uint32_t)(P.L + 1);
+    for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) lut[i] = D.lut[i];
+}
+
+template <bool HAS64, bool HAS32>
+__device__ __forceinline__ double2 load_in(const StageArgs &a, uint32_t j) {
+    double2 v = make_double2(0.0, 0.0);
+    if (HAS64) v = a.in64[j];
+    if (HAS32) {
+        const float2 u = a.in32[j];
+        v.x += (double)u.x;
+        v.y += (double)u.y;
+    }
+    return v;
+}
+
+// One fused stage over one tile. The tile's metadata must already be in LDS
+// (stage_meta) and the coefficient tables too (stage_lut).
+//
+// Every variable has up to 4M hierarchy gathers ("slots"): for each channel
+// k, the row molecule raised (k), lowered (M+k), the column molecule raised
+// (2M+k), lowered (3M+k) (Eqs. uvar-up, uvar-down). Their target indices
+// come from the LDS connection records alone, so all of a thread's gathers
+// are issued together with its own-value load, before the workgroup barrier
+// that publishes the tile's values for the grouped sums.
+template <bool HAS64, bool HAS32>
+__device__ __forceinline__ double2 load_own(const StageArgs &a, uint32_t j) {
+    if (!(a.policy & 1u)) return load_in<HAS64, HAS32>(a, j);
+    double2 v = make_double2(0.0, 0.0);
+    if (HAS64) v = ld_stream(a.in64 + j);
+    if (HAS32) {
+        const fvec2 u = __builtin_nontemporal_load(reinterpret_cast<const fvec2 *>(a.in32 + j));
+        v.x += (double)u.x;
+        v.y += (double)u.y;
+    }
+    return v;
+}
+
+template <int M, bool HAS64, bool HAS32, int BASE, bool EXTRA, bool OUT64, bool TOP>
+__device__ __forceinline__ void process_tile(const InstParams &P, const TileRec &TR, const Smem &S,
+                                             const StageArgs &a, bool first_tile) {
     const uint32_t t = threadIdx.x;
-    double2 res = make_double2(0.0, 0.0);
-    if (t < nloc) {
-        uint32_t lo = 0, hi = npl;  // soff[lo] <= t < start of block hi
+    const bool active = t < TR.nv;
+    enum { TZ = 0, TX = 1, TY = 2, TP = 3, TS = 4 };
+    int kind = TZ, A = 0, B = 0, q = 0, r = 0;
+    uint32_t base = 0, lo = 0;
+    PatHdr H{};
+    CatRec cq{}, cr2{};
+    bool chi = false;
+    uint32_t idx[4 * M];
+    uint32_t live = 0;
+    double2 v[4 * M];
+    double2 own = make_double2(0.0, 0.0);
+    if (active) {
+        uint32_t hi = TR.np;  // block lo holds variable t
         while (hi - lo > 1) {
             uint32_t mid = (lo + hi) >> 1;
-            if (soff[mid] <= t) lo = mid; else hi = mid;
+            if (S.hdr[mid].off - TR.v0 <= t) lo = mid; else hi = mid;
         }
-        const PatHdr H = D.hdr[p0 + lo];
-        const uint32_t base = soff[lo];
+        H = S.hdr[lo];
+        base = H.off - TR.v0;
         const uint32_t loc = t - base;
-        const int G = H.G, G1 = G + 1, nm = G1 * G1;
-        int A, B;
-        bool isT;
+        const int G1 = H.G + 1, nm = G1 * G1;
+        bool isT = false;
         if (loc < (uint32_t)nm) {
             A = (int)loc / G1;
             B = (int)loc - A * G1;
-            isT = false;
         } else {
             uint32_t mask = H.tmask;
             for (int s = (int)loc - nm; s > 0; --s) mask &= mask - 1u;
             A = B = __ffs(mask);  // category index + 1
             isT = true;
         }
-        const int m = P.m, L = P.L;
-        const double *up = D.lut;
-        const double *dn = D.lut + m * (L + 1);
-        const CatRec *cats = D.cat + H.cat_base;
-        const bool chi = H.tier < L;
-        auto mult = [&](int q) -> double {
-            const CatRec c = cats[q];
-            return (c.flags & CAT_ZERO) ? (P.npool - (double)H.r) : (double)c.mult;
+        kind = (A == 0 && B == 0) ? TZ : (B == 0 ? TX : (A == 0 ? TY : ((A == B && !isT) ? TP : TS)));
+        q = A - 1;
+        r = B - 1;
+        chi = TOP ? false : (H.tier < P.L);   // the top tier has no up moves
+        const CatRec *cats = S.cat + (H.cat_base - TR.c0);
+        const Conn *cons = S.con + (H.conn_base - TR.k0);
+        if (A > 0) cq = cats[q];
+        if (B > 0) cr2 = cats[r];
+        const bool rowmv = (kind == TX || kind == TP || kind == TS);
+        const bool colmv = (kind == TY || kind == TS);
+#pragma unroll
+        for (int k = 0; k < M; ++k) {
+            const uint32_t nq = vbyte(cq.vec, k), nr = vbyte(cr2.vec, k);
+            uint32_t dq = cq.conn_off + (chi ? M : 0), dr = cr2.conn_off + (chi ? M : 0);
+            for (int j = 0; j < k; ++j) {
+                dq += vbyte(cq.vec, j) != 0;
+                dr += vbyte(cr2.vec, j) != 0;
+            }
+            const bool l0 = rowmv && kind != TP && chi, l1 = rowmv && nq;
+            const bool l2 = colmv && chi, l3 = colmv && nr;
+            const Conn c0 = l0 ? cons[cq.conn_off + k] : Conn{0u, 0u};
+            const Conn c1 = l1 ? cons[dq] : Conn{0u, 0u};
+            const Conn c2 = l2 ? cons[cr2.conn_off + k] : Conn{0u, 0u};
+            const Conn c3 = l3 ? cons[dr] : Conn{0u, 0u};
+            // row moves: target row = q' of the moved molecule, column = the
+            // column molecule's category in the target (cavity for X)
+            const int q0 = (int)conn_q(c0.info), q1 = (int)conn_q(c1.info);
+            const int q2 = (int)conn_q(c2.info), q3 = (int)conn_q(c3.info);
+            idx[k] = l0 ? tgt_index(c0, q0, kind == TX ? -1 : conn_remap(c0.info, q, r), false) : 0u;
+            idx[M + k] = l1 ? (kind == TP ? tgt_index(c1, q1, q1, true)
+                                          : tgt_index(c1, q1, kind == TX ? -1 : conn_remap(c1.info, q, r), false))
+                            : 0u;
+            idx[2 * M + k] = l2 ? tgt_index(c2, kind == TY ? -1 : conn_remap(c2.info, r, q), q2, false) : 0u;
+            idx[3 * M + k] = l3 ? tgt_index(c3, kind == TY ? -1 : conn_remap(c3.info, r, q), q3, false) : 0u;
+            live |= ((uint32_t)l0 << k) | ((uint32_t)l1 << (M + k)) | ((uint32_t)l2 << (2 * M + k)) |
+                    ((uint32_t)l3 << (3 * M + k));
+        }
+        own = load_own<HAS64, HAS32>(a, TR.v0 + t);
+#pragma unroll
+        for (int j = 0; j < 4 * M; ++j)
+            v[j] = ((live >> j) & 1u) ? load_in<HAS64, HAS32>(a, idx[j]) : make_double2(0.0, 0.0);
+        S.val[t] = own;
+    }
+    __syncthreads();
+
+    double2 res = make_double2(0.0, 0.0);
+    if (active) {
+        const int G = H.G, G1 = G + 1, nm = G1 * G1;
+        const int L1 = P.L + 1;
+        const double *up = S.lut;
+        const double *dn = S.lut + M * L1;
+        const CatRec *cats = S.cat + (H.cat_base - TR.c0);
+        auto mult = [&](int c) -> double {
+            const CatRec cc = cats[c];
+            return (cc.flags & CAT_ZERO) ? (P.npool - (double)H.r) : (double)cc.mult;
         };
-        auto sv = [&](int a, int b) { return sval[base + a * G1 + b]; };
-        auto svT = [&](int q) { return sval[base + nm + __popc(H.tmask & ((1u << q) - 1u))]; };
-
+        auto sv = [&](int x, int y) { return S.val[base + x * G1 + y]; };
+        auto svT = [&](int c) { return S.val[base + nm + __popc(H.tmask & ((1u << c) - 1u))]; };
         double gam = 0.0;
-        for (int k = 0; k < m; ++k) gam += P.nu[k] * (double)vbyte(H.cnt, k);
-        const double g = P.g;
-        const double2 own = sval[t];
-        double2 acc = make_double2(0.0, 0.0);
-        double2 hsum;  // Hamiltonian bracket, multiplied by -i g below
-
-        if (A == 0 && B == 0) {
+#pragma unroll
+        for (int k = 0; k < M; ++k) gam += P.nu[k] * (double)vbyte(H.cnt, k);
+        double2 acc, hsum;  // hsum: Hamiltonian bracket, multiplied by -i g below
+        if (kind == TZ) {
             // Z: -i g sum_q M_q (X_q - Y_q) - (Gamma + kappa) Z   (Eq. HZ)
             hsum = make_double2(0, 0);
-            for (int q = 0; q < G; ++q) hsum = cadd(hsum, cscale(mult(q), csub(sv(q + 1, 0), sv(0, q + 1))));
+            for (int c = 0; c < G; ++c) hsum = cadd(hsum, cscale(mult(c), csub(sv(c + 1, 0), sv(0, c + 1))));
             acc = cscale(-(gam + P.kappa), own);
-        } else if (B == 0) {
-            // X_q: -i(delta)X - i g (Z - R_q) - (Gamma + kappa/2 + Delta) X   (Eq. HX)
-            const int q = A - 1;
-            double2 R = sv(A, A);
-            if ((H.tmask >> q) & 1u) R = cadd(R, cscale(mult(q) - 1.0, svT(q)));
-            for (int r = 0; r < G; ++r)
-                if (r != q) R = cadd(R, cscale(mult(r), sv(A, r + 1)));
-            hsum = csub(sv(0, 0), R);
+        } else if (kind == TX || kind == TY) {
+            // X_q: -i delta X - i g (Z - R_q) - (Gamma + kappa/2 + Delta) X   (Eq. HX)
+            // Y_q: +i delta Y - i g (C_q - Z) - (Gamma + kappa/2 + Delta) Y
+            const bool isX = kind == TX;
+            const int c = isX ? q : r;
+            double2 R = sv(c + 1, c + 1);
+            if ((H.tmask >> c) & 1u) R = cadd(R, cscale(mult(c) - 1.0, svT(c)));
+            for (int x = 0; x < G; ++x)
+                if (x != c) R = cadd(R, cscale(mult(x), isX ? sv(c + 1, x + 1) : sv(x + 1, c + 1)));
+            hsum = isX ? csub(sv(0, 0), R) : csub(R, sv(0, 0));
             const double re = -(gam + 0.5 * P.kappa + P.term);
-            acc = make_double2(re * own.x + P.delta * own.y, re * own.y - P.delta * own.x);
-            const CatRec c = cats[q];
-            for (int k = 0; k < m; ++k) {
-                const uint32_t n = vbyte(c.vec, k);
-                if (chi) {
-                    const Conn cr = D.conn[rec_up(H, c, k)];
-                    const double w = up[k * (L + 1) + n];
-                    cfma(acc, make_double2(0.0, -w), in.load(tgt_index(cr, (int)conn_q(cr.info), -1, false)));
-                }
-                if (n) {
-                    const Conn cr = D.conn[rec_dn(H, c, k, chi, m)];
-                    const double w = dn[k * (L + 1) + n];
-                    // -i w c_k
-                    cfma(acc, make_double2(w * P.ci[k], -w * P.cr[k]), in.load(tgt_index(cr, (int)conn_q(cr.info), -1, false)));
-                }
-            }
-        } else if (A == 0) {
-            // Y_q: +i(delta)Y - i g (C_q - Z) - (Gamma + kappa/2 + Delta) Y
-            const int q = B - 1;
-            double2 C = sv(B, B);
-            if ((H.tmask >> q) & 1u) C = cadd(C, cscale(mult(q) - 1.0, svT(q)));
-            for (int r = 0; r < G; ++r)
-                if (r != q) C = cadd(C, cscale(mult(r), sv(r + 1, B)));
-            hsum = csub(C, sv(0, 0));
-            const double re = -(gam + 0.5 * P.kappa + P.term);
-            acc = make_double2(re * own.x - P.delta * own.y, re * own.y + P.delta * own.x);
-            const CatRec c = cats[q];
-            for (int k = 0; k < m; ++k) {
-                const uint32_t n = vbyte(c.vec, k);
-                if (chi) {
-                    const Conn cr = D.conn[rec_up(H, c, k)];
-                    const double w = up[k * (L + 1) + n];
-                    cfma(acc, make_double2(0.0, w), in.load(tgt_index(cr, -1, (int)conn_q(cr.info), false)));
-                }
-                if (n) {
-                    const Conn cr = D.conn[rec_dn(H, c, k, chi, m)];
-                    const double w = dn[k * (L + 1) + n];
-                    // +i w cc_k
-                    cfma(acc, make_double2(-w * P.cci[k], w * P.ccr[k]), in.load(tgt_index(cr, -1, (int)conn_q(cr.info), false)));
-                }
-            }
-        } else if (A == B && !isT) {
-            // P_q: -i g (Y_q - X_q) - Gamma P; down only, coefficient -i w (c_k - cc_k)
-            const int q = A - 1;
+            const double dl = isX ? P.delta : -P.delta;
+            acc = make_double2(re * own.x + dl * own.y, re * own.y - dl * own.x);
+        } else if (kind == TP) {
+            // P_q: -i g (Y_q - X_q) - Gamma P
             hsum = csub(sv(0, A), sv(A, 0));
             acc = cscale(-gam, own);
-            const CatRec c = cats[q];
-            for (int k = 0; k < m; ++k) {
-                const uint32_t n = vbyte(c.vec, k);
-                if (!n) continue;
-                const Conn cr = D.conn[rec_dn(H, c, k, chi, m)];
-                const double w = dn[k * (L + 1) + n];
-                const double dr = P.cr[k] - P.ccr[k], di = P.ci[k] - P.cci[k];
-                const int qn = (int)conn_q(cr.info);
-                cfma(acc, make_double2(w * di, -w * dr), in.load(tgt_index(cr, qn, qn, true)));
-            }
         } else {
-            // S_{q,r} (q = A-1, r = B-1) or T_q (q = r): -i g (Y_r - X_q) - (Gamma + 2 Delta) V
-            const int q = A - 1, r = B - 1;
+            // S_{q,r} or T_q: -i g (Y_r - X_q) - (Gamma + 2 Delta) V
             hsum = csub(sv(0, B), sv(A, 0));
             acc = cscale(-(gam + 2.0 * P.term), own);
-            // row term: the row molecule (category q) moves
-            {
-                const CatRec c = cats[q];
-                for (int k = 0; k < m; ++k) {
-                    const uint32_t n = vbyte(c.vec, k);
-                    if (chi) {
-                        const Conn cr = D.conn[rec_up(H, c, k)];
-                        const double w = up[k * (L + 1) + n];
-                        const int a2 = (int)conn_q(cr.info), b2 = conn_remap(cr.info, q, r);
-                        cfma(acc, make_double2(0.0, -w), in.load(tgt_index(cr, a2, b2, false)));
-                    }
-                    if (n) {
-                        const Conn cr = D.conn[rec_dn(H, c, k, chi, m)];
-                        const double w = dn[k * (L + 1) + n];
-                        const int a2 = (int)conn_q(cr.info), b2 = conn_remap(cr.info, q, r);
-                        cfma(acc, make_double2(w * P.ci[k], -w * P.cr[k]), in.load(tgt_index(cr, a2, b2, false)));
-                    }
-                }
-            }
-            // column term: the column molecule (category r) moves
-            {
-                const CatRec c = cats[r];
-                for (int k = 0; k < m; ++k) {
-                    const uint32_t n = vbyte(c.vec, k);
-                    if (chi) {
-                        const Conn cr = D.conn[rec_up(H, c, k)];
-                        const double w = up[k * (L + 1) + n];
-                        const int b2 = (int)conn_q(cr.info), a2 = conn_remap(cr.info, r, q);
-                        cfma(acc, make_double2(0.0, w), in.load(tgt_index(cr, a2, b2, false)));
-                    }
-                    if (n) {
-                        const Conn cr = D.conn[rec_dn(H, c, k, chi, m)];
-                        const double w = dn[k * (L + 1) + n];
-                        const int b2 = (int)conn_q(cr.info), a2 = conn_remap(cr.info, r, q);
-                        cfma(acc, make_double2(-w * P.cci[k], w * P.ccr[k]), in.load(tgt_index(cr, a2, b2, false)));
-                    }
-                }
-            }
         }
-        // -i g * hsum
-        acc.x += g * hsum.y;
-        acc.y -= g * hsum.x;
+        // hierarchy: row moves -i sqrt((n+1)|c|), -i sqrt(n/|c|) c_k (P: c_k - cc_k);
+        // column moves +i sqrt((n+1)|c|), +i sqrt(n/|c|) cc_k
+#pragma unroll
+        for (int k = 0; k < M; ++k) {
+            const uint32_t nq = vbyte(cq.vec, k), nr = vbyte(cr2.vec, k);
+            const double uq = up[k * L1 + nq], dq = dn[k * L1 + nq];
+            const double ur = up[k * L1 + nr], dr = dn[k * L1 + nr];
+            const double cre = kind == TP ? P.cr[k] - P.ccr[k] : P.cr[k];
+            const double cim = kind == TP ? P.ci[k] - P.cci[k] : P.ci[k];
+            cfma(acc, make_double2(0.0, -uq), v[k]);
+            cfma(acc, make_double2(dq * cim, -dq * cre), v[M + k]);
+            cfma(acc, make_double2(0.0, ur), v[2 * M + k]);
+            cfma(acc, make_double2(-dr * P.cci[k], dr * P.ccr[k]), v[3 * M + k]);
+        }
+        acc.x += P.g * hsum.y;
+        acc.y -= P.g * hsum.x;
         if (EXTRA) {
-            const float2 e = extra[v0 + t];
-            acc.x += extra_scale * (double)e.x;
-            acc.y += extra_scale * (double)e.y;
+            const float2 e = a.extra[TR.v0 + t];
+            acc.x += a.extra_scale * (double)e.x;
+            acc.y += a.extra_scale * (double)e.y;
         }
-        res = cscale(alpha, acc);
-        if (BASE_Y) res = cadd(res, BASE_IS_IN ? own : ybase[v0 + t]);
-        store(out + v0 + t, res);
+        res = cscale(a.alpha, acc);
+        if (BASE == BASE_IN) res = cadd(res, own);
+        if (BASE == BASE_Y) res = cadd(res, (a.policy & 2u) ? ld_stream(a.ybase + TR.v0 + t) : a.ybase[TR.v0 + t]);
+        if (a.policy & 4u) {
+            if (OUT64) st_stream(a.out64 + TR.v0 + t, res);
+            else st_stream(a.out32 + TR.v0 + t, res);
+        } else {
+            if (OUT64) a.out64[TR.v0 + t] = res;
+            else a.out32[TR.v0 + t] = make_float2((float)res.x, (float)res.y);
+        }
     }
-    if (obs != nullptr && tile == 0) {
+    __syncthreads();
+    if (a.obs != nullptr && first_tile) {
         // the empty pattern is the first block of tile 0: evaluate the
-        // observables of the freshly written tier-0 block
+        // observables of the freshly computed tier-0 block
+        const uint32_t n0 = S.hdr[0].size;
+        if (t < n0) S.val[t] = res;
         __syncthreads();
-        const uint32_t n0 = D.hdr[0].size;
-        if (t < n0) sval[t] = res;
+        if (t == 0) tier0_observables(P, S.hdr[0], S.cat, S.val, a.obs);
         __syncthreads();
-        if (t == 0) tier0_observables(P, D.hdr[0], D.cat, sval, obs);
+    }
+}
+
+// One launch = one stage over all tiles (used by heom_rhs and as the
+// non-persistent path).
+template <int M, bool HAS64, bool HAS32, int BASE, bool EXTRA, bool OUT64, bool TOP>
+__global__ __launch_bounds__(MAX_TILE) void stage_kernel(Dev D, StageArgs a, int xcd) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const InstParams &P = *D.ip;
+    const Smem S = carve(smem, P);
+    const uint32_t tile = a.tile0 + (xcd ? xcd_tile(blockIdx.x, gridDim.x) : blockIdx.x);
+    const TileRec TR = D.tiles[tile];
+    stage_meta(D, TR, S);
+    stage_lut(D, P, S.lut);
+    __syncthreads();
+    process_tile<M, HAS64, HAS32, BASE, EXTRA, OUT64, TOP>(P, TR, S, a, tile == 0);
+}
+
+// Grid-wide barrier for the persistent kernel. Workgroup w publishes its
+// arrival by a release store of `epoch` into its own flag slot (flags are 64
+// bytes apart); every workgroup then polls all slots, one per thread, until
+// each holds at least `epoch`. No read-modify-write is shared between
+// workgroups. A bounded wait: after `limit` polling rounds the workgroup sets
+// the timeout word and returns false, and every workgroup then leaves the
+// kernel.
+__device__ __forceinline__ bool grid_barrier(uint32_t *flags, uint32_t *timeout, uint32_t epoch, uint32_t limit) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __syncthreads();
+    const uint32_t W = gridDim.x;
+    if (threadIdx.x == 0)
+        __hip_atomic_store(flags + 16u * blockIdx.x, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    uint32_t polls = 0;  // counted by thread 0 only
+    bool ok = true;
+    while (true) {
+        int mine = 1;
+        for (uint32_t i = threadIdx.x; i < W; i += blockDim.x)
+            mine &= __hip_atomic_load(flags + 16u * i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= epoch;
+        int stop = 0;
+        if (threadIdx.x == 0)
+            stop = (__hip_atomic_load(timeout, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) || (++polls > limit);
+        // every thread reaches both workgroup reductions in every round
+        const int all = __syncthreads_and(mine);
+        const int any_stop = __syncthreads_or(stop);
+        if (all) break;
+        if (any_stop) {
+            if (threadIdx.x == 0) __hip_atomic_store(timeout, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            ok = false;
+            break;
+        }
+        __builtin_amdgcn_s_sleep(1);
+    }
+    __syncthreads();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    return ok;
+}
+
+struct PersistArgs {
+    double2 *y;         // state (FP64), updated in place
+    double2 *w0, *w1;   // FP64 stage vectors, or y2 (w0) for FP32
+    float2 *u1, *u2;    // FP32 increments
+    double dt;
+    int64_t step0;      // index of the first step of this launch (for observables)
+    int64_t nsteps;
+    int64_t obs_every;
+    double *obs;
+    uint32_t *flags;    // one 64-byte slot per workgroup
+    uint32_t *timeout;  // set when a barrier gives up
+    uint32_t limit;
+    uint32_t policy;    // cache hints, as StageArgs::policy
+};
+
+// All RK4 steps of heom_propagate in one cooperative launch: every workgroup
+// owns a fixed set of tiles (a contiguous run per XCD), processes its tiles
+// for each of the four stages, and meets the grid at a barrier after each
+// stage. A workgroup that owns a single tile keeps its metadata in LDS for the
+// whole launch.
+template <int M, int PREC>
+__global__ __launch_bounds__(MAX_TILE) void persistent_kernel(Dev D, PersistArgs pa) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const InstParams &P = *D.ip;
+    const Smem S = carve(smem, P);
+    const uint32_t T = P.n_tiles, W = gridDim.x, w = blockIdx.x;
+    // tiles of this workgroup: XCD x = w % 8 owns tiles [x*T/8, (x+1)*T/8)
+    const uint32_t X = W < 8 ? W : 8;
+    const uint32_t x = w % X, j = w / X;
+    const uint32_t wx = W / X + (x < W % X ? 1u : 0u);
+    const uint32_t t_lo = (uint32_t)((uint64_t)x * T / X), t_hi = (uint32_t)((uint64_t)(x + 1) * T / X);
+    const bool single = (t_hi - t_lo) <= wx;
+    stage_lut(D, P, S.lut);
+    TileRec TR0 = {};
+    if (single && t_lo + j < t_hi) {
+        TR0 = D.tiles[t_lo + j];
+        stage_meta(D, TR0, S);
+    }
+    __syncthreads();
+    const double h = pa.dt;
+    const double al[4] = {h / 4.0, h / 3.0, h / 2.0, h};
+    uint32_t epoch = 0;
+    double2 *cur = pa.y, *nxt = pa.w0;
+    for (int64_t st = 1; st <= pa.nsteps; ++st) {
+        const int64_t gst = pa.step0 + st;
+        double *ob = (pa.obs != nullptr && pa.obs_every > 0 && gst % pa.obs_every == 0)
+                         ? pa.obs + (gst / pa.obs_every) * HEOM_NOBS : nullptr;
+        for (int s = 0; s < 4; ++s) {
+            StageArgs a{};
+            a.alpha = al[s];
+            if (PREC == HEOM_FP64) {
+                a.in64 = s == 0 ? pa.y : (s == 2 ? pa.w1 : pa.w0);
+                a.ybase = pa.y;
+                a.out64 = s == 3 ? pa.y : (s == 1 ? pa.w1 : pa.w0);
+            } else {
+                a.in64 = (s == 0 || s == 3) ? cur : nullptr;
+                a.in32 = s == 1 ? pa.u1 : (s == 2 ? pa.u2 : (s == 3 ? pa.u1 : nullptr));
+                a.extra = pa.u1;
+                a.extra_scale = 4.0 / h;
+                a.ybase = cur;
+                a.out32 = s == 1 ? pa.u2 : pa.u1;
+                a.out64 = nxt;
+            }
+            a.obs = s == 3 ? ob : nullptr;
+            a.policy = pa.policy;
+            for (uint32_t tl = t_lo + j; tl < t_hi; tl += wx) {
+                const TileRec TR = single ? TR0 : D.tiles[tl];
+                if (!single) {
+                    stage_meta(D, TR, S);
+                    __syncthreads();
+                }
+                if (PREC == HEOM_FP64) {
+                    if (s == 0) process_tile<M, true, false, BASE_IN, false, true, false>(P, TR, S, a, tl == 0);
+                    else process_tile<M, true, false, BASE_Y, false, true, false>(P, TR, S, a, tl == 0);
+                } else {
+                    if (s == 0) process_tile<M, true, false, BASE_NONE, false, false, false>(P, TR, S, a, false);
+                    else if (s < 3) process_tile<M, false, true, BASE_NONE, true, false, false>(P, TR, S, a, false);
+                    else process_tile<M, true, true, BASE_Y, false, true, false>(P, TR, S, a, tl == 0);
+                }
+            }
+            epoch += 1;
+            if (!grid_barrier(pa.flags, pa.timeout, epoch, pa.limit)) return;
+        }
+        if (PREC != HEOM_FP64) {
+            double2 *tmp = cur;
+            cur = nxt;
+            nxt = tmp;
+        }
+    }
+    if (PREC != HEOM_FP64 && cur != pa.y) {
+        // an odd number of steps leaves the state in the second buffer
+        for (uint32_t i = w * blockDim.x + threadIdx.x; i < P.n_var; i += W * blockDim.x) pa.y[i] = cur[i];
     }
 }
 
@@ -391,17 +609,89 @@ __global__ void copy_kernel(const double2 *src, double2 *dst, uint32_t n) {
         dst[i] = src[i];
 }
 
-int g_xcd_map = 1;
+template <int M, bool HAS64, bool HAS32, int BASE, bool EXTRA, bool OUT64>
+void launch_m(const HostTables &t, hipStream_t s, StageArgs a) {
+    a.policy = (uint32_t)t.tune.cache_policy;
+    const uint32_t T = (uint32_t)t.tiles.size();
+    // Large states: the top tier (no up moves) runs in its own launch with a
+    // kernel that has no up-move slots, fewer registers and more waves.
+    const uint32_t split = (T >= 2048 && t.top_tile > 0 && t.top_tile < T) ? t.top_tile : T;
+    a.tile0 = 0;
+    hipLaunchKernelGGL((stage_kernel<M, HAS64, HAS32, BASE, EXTRA, OUT64, false>), dim3(split),
+                       dim3(t.tile_vars), t.lds_bytes, s, dev_view(t), a, t.tune.xcd_map);
+    if (split < T) {
+        a.tile0 = split;
+        hipLaunchKernelGGL((stage_kernel<M, HAS64, HAS32, BASE, EXTRA, OUT64, true>), dim3(T - split),
+                           dim3(t.tile_vars), t.lds_bytes, s, dev_view(t), a, t.tune.xcd_map);
+    }
+}
 
-template <class IN, class OutT, bool BASE_Y, bool BASE_IS_IN, bool EXTRA>
-int launch_stage(const HostTables &t, hipStream_t s, IN in, const double2 *ybase, const float2 *extra,
-                 double extra_scale, OutT *out, double alpha, double *obs) {
-    const uint32_t ntiles = (uint32_t)(t.tiles.size() - 1);
-    hipLaunchKernelGGL((stage_kernel<IN, OutT, BASE_Y, BASE_IS_IN, EXTRA>), dim3(ntiles), dim3(t.tile_vars), 0, s,
-                       dev_view(t), in, ybase, extra, extra_scale, out, alpha, obs, g_xcd_map);
+template <bool HAS64, bool HAS32, int BASE, bool EXTRA, bool OUT64>
+int launch_stage(const HostTables &t, hipStream_t s, const StageArgs &a) {
+#define HEOM_CASE(MM) \
+    case MM: launch_m<MM, HAS64, HAS32, BASE, EXTRA, OUT64>(t, s, a); break;
+    switch (t.m) {
+        HEOM_CASE(1) HEOM_CASE(2) HEOM_CASE(3) HEOM_CASE(4)
+        HEOM_CASE(5) HEOM_CASE(6) HEOM_CASE(7) HEOM_CASE(8)
+        default: return fail(HEOM_E_UNSUPPORTED, "m out of range");
+    }
+#undef HEOM_CASE
     HIP_TRY(hipGetLastError());
     return HEOM_OK;
 }
+
+__global__ void zero_u32_kernel(uint32_t *p, uint32_t n) {
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = 0u;
+}
+
+// Control area of the work buffer, after the state-sized vectors:
+//   byte 4: barrier timeout word; bytes 256..: one 64-byte flag slot per
+//   persistent workgroup.
+constexpr uint32_t MAX_PERSIST_WG = 2048;
+constexpr size_t CTRL_BYTES = 256 + 64 * (size_t)MAX_PERSIST_WG;
+
+template <int M, int PREC>
+int launch_persistent_m(const HostTables &t, hipStream_t s, PersistArgs pa, bool *used) {
+    auto kern = persistent_kernel<M, PREC>;
+    int dev = 0, ncu = 0, per_cu = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    HIP_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, t.tile_vars, t.lds_bytes));
+    if (per_cu < 1) { *used = false; return HEOM_OK; }
+    uint64_t nwg = std::min<uint64_t>((uint64_t)per_cu * (uint64_t)ncu, t.tiles.size());
+    nwg = std::min<uint64_t>(nwg, MAX_PERSIST_WG);
+    if (t.tune.max_workgroups > 0) nwg = std::min<uint64_t>(nwg, (uint64_t)t.tune.max_workgroups);
+    // barrier epochs (4 per step) must not wrap within one launch
+    const int64_t chunk = (int64_t)1 << 28;
+    const int64_t total = pa.nsteps;
+    Dev D = dev_view(t);
+    for (int64_t done = 0; done < total; done += chunk) {
+        PersistArgs a = pa;
+        a.step0 = pa.step0 + done;
+        a.nsteps = std::min<int64_t>(chunk, total - done);
+        hipLaunchKernelGGL(zero_u32_kernel, dim3(64), dim3(256), 0, s, pa.flags - 64, (uint32_t)(CTRL_BYTES / 4));
+        HIP_TRY(hipGetLastError());
+        void *args[] = {&D, &a};
+        HIP_TRY(hipLaunchCooperativeKernel(reinterpret_cast<const void *>(kern), dim3((uint32_t)nwg),
+                                           dim3(t.tile_vars), args, t.lds_bytes, s));
+    }
+    *used = true;
+    return HEOM_OK;
+}
+
+int launch_persistent(const HostTables &t, hipStream_t s, const PersistArgs &pa, int prec, bool *used) {
+#define HEOM_PCASE(MM) \
+    case MM: return prec == HEOM_FP64 ? launch_persistent_m<MM, HEOM_FP64>(t, s, pa, used) \
+                                      : launch_persistent_m<MM, HEOM_FP32>(t, s, pa, used);
+    switch (t.m) {
+        HEOM_PCASE(1) HEOM_PCASE(2) HEOM_PCASE(3) HEOM_PCASE(4)
+        HEOM_PCASE(5) HEOM_PCASE(6) HEOM_PCASE(7) HEOM_PCASE(8)
+        default: return fail(HEOM_E_UNSUPPORTED, "m out of range");
+    }
+#undef HEOM_PCASE
+}
+
+size_t work_bytes_for(const HostTables &t) { return (size_t)t.n_var * 32 + CTRL_BYTES; }
 
 int check_ready(const heom_tables *h) {
     if (!h) return fail(HEOM_E_INVAL, "tables handle is NULL");
@@ -463,11 +753,11 @@ int heom_table_info(const heom_tables *h, heom_sizes *out) {
     out->n_patterns = (int64_t)t.hdr.size();
     out->n_var = t.n_var;
     out->n_conn = (int64_t)t.conn.size();
-    out->n_tiles = (int64_t)t.tiles.size() - 1;
+    out->n_tiles = (int64_t)t.tiles.size();
     out->n_categories = (int64_t)t.cat.size();
     out->table_bytes = (int64_t)t.image.size();
-    out->work_bytes_fp64 = (int64_t)t.n_var * 32;
-    out->work_bytes_fp32 = (int64_t)t.n_var * 32;
+    out->work_bytes_fp64 = (int64_t)work_bytes_for(t);
+    out->work_bytes_fp32 = (int64_t)work_bytes_for(t);
     out->tier0_size = (int64_t)tier0_size(t);
     out->max_G = t.max_G;
     out->tile_vars = t.tile_vars;
@@ -539,10 +829,11 @@ int heom_rhs(const heom_tables *h, const void *y_dev, void *dy_dev, void *stream
     if (int rc = check_dev(y_dev, "y_dev")) return rc;
     if (int rc = check_dev(dy_dev, "dy_dev")) return rc;
     if (y_dev == dy_dev) return fail(HEOM_E_INVAL, "y_dev and dy_dev must differ");
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    return launch_stage<InF64, double2, false, false, false>(h->t, s, InF64{static_cast<const double2 *>(y_dev)},
-                                                             nullptr, nullptr, 0.0, static_cast<double2 *>(dy_dev),
-                                                             1.0, nullptr);
+    StageArgs a{};
+    a.in64 = static_cast<const double2 *>(y_dev);
+    a.out64 = static_cast<double2 *>(dy_dev);
+    a.alpha = 1.0;
+    return launch_stage<true, false, BASE_NONE, false, true>(h->t, static_cast<hipStream_t>(stream), a);
 }
 
 int heom_observables(const heom_tables *h, const void *y_dev, double *obs_dev, void *stream) {
@@ -566,37 +857,74 @@ int heom_propagate(const heom_tables *h, void *y_dev, void *work_dev, size_t wor
     if (precision != HEOM_FP64 && precision != HEOM_FP32) return fail(HEOM_E_INVAL, "unknown precision");
     const HostTables &t = h->t;
     const size_t n = t.n_var;
-    if (work_bytes < n * 32) return fail(HEOM_E_TOO_LARGE, "work buffer smaller than work_bytes");
+    if (work_bytes < work_bytes_for(t)) return fail(HEOM_E_TOO_LARGE, "work buffer smaller than work_bytes");
     hipStream_t s = static_cast<hipStream_t>(stream);
     double2 *y = static_cast<double2 *>(y_dev);
     if (obs_every > 0) {
         hipLaunchKernelGGL(observables_kernel, dim3(1), dim3(64), 0, s, dev_view(t), y, obs_dev);
         HIP_TRY(hipGetLastError());
     }
+    if (nsteps == 0) return HEOM_OK;
+    unsigned char *wb = static_cast<unsigned char *>(work_dev);
+    PersistArgs pa{};
+    pa.y = y;
+    pa.dt = dt;
+    pa.step0 = 0;
+    pa.nsteps = nsteps;
+    pa.obs_every = obs_every;
+    pa.obs = obs_every > 0 ? obs_dev : nullptr;
+    pa.timeout = reinterpret_cast<uint32_t *>(wb + 32 * n + 4);
+    pa.flags = reinterpret_cast<uint32_t *>(wb + 32 * n + 256);
+    pa.limit = t.tune.spin_limit > 0 ? (uint32_t)t.tune.spin_limit : (1u << 20);
+    pa.policy = (uint32_t)t.tune.cache_policy;
+    if (precision == HEOM_FP64) {
+        pa.w0 = reinterpret_cast<double2 *>(wb);
+        pa.w1 = pa.w0 + n;
+    } else {
+        pa.w0 = reinterpret_cast<double2 *>(wb);
+        pa.u1 = reinterpret_cast<float2 *>(wb + 16 * n);
+        pa.u2 = pa.u1 + n;
+    }
+    hipLaunchKernelGGL(zero_u32_kernel, dim3(64), dim3(256), 0, s, pa.timeout - 1, (uint32_t)(CTRL_BYTES / 4));
+    HIP_TRY(hipGetLastError());
+    const bool persist = t.tune.persistent == 1 || (t.tune.persistent == 2 && t.tiles.size() <= 256);
+    if (persist) {
+        bool used = false;
+        if (int rc = launch_persistent(t, s, pa, precision, &used)) return rc;
+        if (used) return HEOM_OK;
+    }
+    // one launch per stage
     const double h1 = dt / 4.0, h2 = dt / 3.0, h3 = dt / 2.0, h4 = dt;
     int rc;
     if (precision == HEOM_FP64) {
-        double2 *wa = static_cast<double2 *>(work_dev);
-        double2 *wb = wa + n;
+        double2 *wa = pa.w0, *wbv = pa.w1;
         for (int64_t st = 1; st <= nsteps; ++st) {
             double *ob = (obs_every > 0 && st % obs_every == 0) ? obs_dev + (st / obs_every) * HEOM_NOBS : nullptr;
-            if ((rc = launch_stage<InF64, double2, true, true, false>(t, s, InF64{y}, y, nullptr, 0.0, wa, h1, nullptr))) return rc;
-            if ((rc = launch_stage<InF64, double2, true, false, false>(t, s, InF64{wa}, y, nullptr, 0.0, wb, h2, nullptr))) return rc;
-            if ((rc = launch_stage<InF64, double2, true, false, false>(t, s, InF64{wb}, y, nullptr, 0.0, wa, h3, nullptr))) return rc;
-            if ((rc = launch_stage<InF64, double2, true, false, false>(t, s, InF64{wa}, y, nullptr, 0.0, y, h4, ob))) return rc;
+            StageArgs a{};
+            a.in64 = y; a.out64 = wa; a.alpha = h1;
+            if ((rc = launch_stage<true, false, BASE_IN, false, true>(t, s, a))) return rc;
+            a = StageArgs{}; a.in64 = wa; a.ybase = y; a.out64 = wbv; a.alpha = h2;
+            if ((rc = launch_stage<true, false, BASE_Y, false, true>(t, s, a))) return rc;
+            a = StageArgs{}; a.in64 = wbv; a.ybase = y; a.out64 = wa; a.alpha = h3;
+            if ((rc = launch_stage<true, false, BASE_Y, false, true>(t, s, a))) return rc;
+            a = StageArgs{}; a.in64 = wa; a.ybase = y; a.out64 = y; a.alpha = h4; a.obs = ob;
+            if ((rc = launch_stage<true, false, BASE_Y, false, true>(t, s, a))) return rc;
         }
     } else {
-        double2 *y2 = static_cast<double2 *>(work_dev);
-        float2 *u1 = reinterpret_cast<float2 *>(y2 + n);
-        float2 *u2 = u1 + n;
-        double2 *cur = y, *nxt = y2;
+        double2 *cur = y, *nxt = pa.w0;
+        float2 *u1 = pa.u1, *u2 = pa.u2;
         const double inv_h1 = 1.0 / h1;
         for (int64_t st = 1; st <= nsteps; ++st) {
             double *ob = (obs_every > 0 && st % obs_every == 0) ? obs_dev + (st / obs_every) * HEOM_NOBS : nullptr;
-            if ((rc = launch_stage<InF64, float2, false, false, false>(t, s, InF64{cur}, nullptr, nullptr, 0.0, u1, h1, nullptr))) return rc;
-            if ((rc = launch_stage<InF32, float2, false, false, true>(t, s, InF32{u1}, nullptr, u1, inv_h1, u2, h2, nullptr))) return rc;
-            if ((rc = launch_stage<InF32, float2, false, false, true>(t, s, InF32{u2}, nullptr, u1, inv_h1, u1, h3, nullptr))) return rc;
-            if ((rc = launch_stage<InSum, double2, true, false, false>(t, s, InSum{cur, u1}, cur, nullptr, 0.0, nxt, h4, ob))) return rc;
+            StageArgs a{};
+            a.in64 = cur; a.out32 = u1; a.alpha = h1;
+            if ((rc = launch_stage<true, false, BASE_NONE, false, false>(t, s, a))) return rc;
+            a = StageArgs{}; a.in32 = u1; a.extra = u1; a.extra_scale = inv_h1; a.out32 = u2; a.alpha = h2;
+            if ((rc = launch_stage<false, true, BASE_NONE, true, false>(t, s, a))) return rc;
+            a = StageArgs{}; a.in32 = u2; a.extra = u1; a.extra_scale = inv_h1; a.out32 = u1; a.alpha = h3;
+            if ((rc = launch_stage<false, true, BASE_NONE, true, false>(t, s, a))) return rc;
+            a = StageArgs{}; a.in64 = cur; a.in32 = u1; a.ybase = cur; a.out64 = nxt; a.alpha = h4; a.obs = ob;
+            if ((rc = launch_stage<true, true, BASE_Y, false, true>(t, s, a))) return rc;
             std::swap(cur, nxt);
         }
         if (cur != y) {
@@ -604,6 +932,45 @@ int heom_propagate(const heom_tables *h, void *y_dev, void *work_dev, size_t wor
             HIP_TRY(hipGetLastError());
         }
     }
+    return HEOM_OK;
+}
+
+int heom_set_tuning(heom_tables *h, const heom_tuning *tu) {
+    if (!h || !tu) return fail(HEOM_E_INVAL, "NULL argument");
+    HostTables &t = h->t;
+    if (tu->tile_vars != 0 && tu->tile_vars != t.tile_vars) {
+        std::string err;
+        if (int rc = make_tiles(&t, tu->tile_vars, &err)) return fail(rc, err);
+    }
+    if (tu->persistent < 0 || tu->persistent > 2) return fail(HEOM_E_INVAL, "persistent must be 0, 1 or 2");
+    t.tune.persistent = tu->persistent;
+    t.tune.xcd_map = tu->xcd_map ? 1 : 0;
+    t.tune.max_workgroups = tu->max_workgroups;
+    t.tune.spin_limit = tu->spin_limit;
+    if (tu->cache_policy < 0 || tu->cache_policy > 7) return fail(HEOM_E_INVAL, "cache_policy must be 0..7");
+    t.tune.cache_policy = tu->cache_policy;
+    return HEOM_OK;
+}
+
+int heom_work_status(const heom_tables *h, const void *work_dev, size_t work_bytes, void *stream) {
+    if (!h || !work_dev) return fail(HEOM_E_INVAL, "NULL argument");
+    if (work_bytes < work_bytes_for(h->t)) return fail(HEOM_E_TOO_LARGE, "work buffer smaller than work_bytes");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    uint32_t flag = 0;
+    const unsigned char *p = static_cast<const unsigned char *>(work_dev) + 32 * (size_t)h->t.n_var + 4;
+    HIP_TRY(hipMemcpyAsync(&flag, p, 4, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return flag ? fail(HEOM_E_TIMEOUT, "a grid barrier of the persistent kernel timed out") : HEOM_OK;
+}
+
+int heom_get_tuning(const heom_tables *h, heom_tuning *tu) {
+    if (!h || !tu) return fail(HEOM_E_INVAL, "NULL argument");
+    tu->tile_vars = h->t.tile_vars;
+    tu->persistent = h->t.tune.persistent;
+    tu->xcd_map = h->t.tune.xcd_map;
+    tu->max_workgroups = h->t.tune.max_workgroups;
+    tu->spin_limit = h->t.tune.spin_limit;
+    tu->cache_policy = h->t.tune.cache_policy;
     return HEOM_OK;
 }
 

@@ -73,6 +73,16 @@ HEOM_HD int conn_remap(uint32_t info, int q, int r) {
     return r1 + ((conn_new(info) && r1 >= (int)conn_q(info)) ? 1 : 0);
 }
 
+// One workgroup tile: a run of whole patterns and the contiguous ranges of
+// their variables, categories and connection records. 32 bytes.
+struct TileRec {
+    uint32_t p0, np;     // patterns
+    uint32_t v0, nv;     // unique variables
+    uint32_t c0, nc;     // category records
+    uint32_t k0, nk;     // connection records
+};
+static_assert(sizeof(TileRec) == 32, "TileRec layout");
+
 // Per-instance numeric parameters (device image header). 256-byte aligned.
 struct InstParams {
     double g;          // single-molecule coupling
@@ -87,7 +97,7 @@ struct InstParams {
     double cr[HEOM_MAX_M], ci[HEOM_MAX_M];      // c_k
     double ccr[HEOM_MAX_M], cci[HEOM_MAX_M];    // c_check_k
     int32_t m, L, d, n_pat;
-    uint32_t n_var, n_tiles, tile_vars, pad;
+    uint32_t n_var, n_tiles, tile_vars, max_np, max_nc, max_nk, lds_bytes, pad;
     // byte offsets of the sections from the image base
     uint64_t off_lut, off_hdr, off_cat, off_conn, off_tile;
 };
@@ -105,7 +115,8 @@ struct HostTables {
     std::vector<CatRec> cat;
     std::vector<Conn> conn;
     std::vector<uint32_t> conn_target;  // target pattern index per Conn
-    std::vector<uint32_t> tiles;        // first pattern of each tile, then n_pat
+    std::vector<TileRec> tiles;         // workgroup tiles
+    uint32_t max_np = 0, max_nc = 0, max_nk = 0, lds_bytes = 0;
     std::vector<uint16_t> pat_ids;      // flat: d dist ids + pool ids
     std::vector<uint32_t> pat_start;    // per pattern start in pat_ids, then end
     uint32_t n_var = 0;
@@ -113,6 +124,8 @@ struct HostTables {
     int64_t hier_gathers = 0;
     std::vector<double> lut;            // up[k][n] then dn[k][n]
     std::vector<unsigned char> image;   // device image (host staging)
+    heom_tuning tune{0, 0, 0, 0, 0, 6};  // tile_vars unused here; persistent, xcd_map, max_workgroups, spin_limit, cache_policy
+    uint32_t top_tile = 0;              // first tile whose patterns are all in tier L
     void *dev = nullptr;                // uploaded image
     size_t dev_bytes = 0;
     bool uploaded = false;
@@ -121,6 +134,7 @@ struct HostTables {
 // host-side helpers implemented in tables.cpp
 int build(const heom_problem *p, HostTables *t, std::string *err);
 int set_params(HostTables *t, const heom_problem *p, std::string *err);
+int make_tiles(HostTables *t, int tile_vars, std::string *err);
 void pack_image(HostTables *t);
 size_t tier0_size(const HostTables &t);
 

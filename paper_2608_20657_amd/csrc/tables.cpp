@@ -385,20 +385,62 @@ int build(const heom_problem *p, HostTables *t, std::string *err) {
         t->hier_gathers += g;
     }
 
-    // tiles: greedy runs of whole patterns, at most tile_vars variables
     uint32_t maxblk = 0;
     for (auto &h : t->hdr) maxblk = std::max(maxblk, h.size);
-    t->tile_vars = maxblk <= 256 ? 256 : 512;
-    t->tiles.clear();
-    uint32_t acc = 0;
-    for (size_t i = 0; i < np; ++i) {
-        if (i == 0 || acc + t->hdr[i].size > (uint32_t)t->tile_vars) {
-            t->tiles.push_back((uint32_t)i);
-            acc = 0;
-        }
-        acc += t->hdr[i].size;
+    // default tile (measured on MI355X): 64 variables for states below 2^17
+    // variables (more workgroups in flight for a latency-bound stage), 256
+    // above; never below the largest block
+    int tv = t->n_var <= (1u << 17) ? 64 : 256;
+    while ((uint32_t)tv < maxblk) tv *= 2;
+    if ((rc = make_tiles(t, tv, err))) return rc;
+    t->uploaded = false;
+    pack_image(t);
+    return HEOM_OK;
+}
+
+int make_tiles(HostTables *t, int tile_vars, std::string *err) {
+    uint32_t maxblk = 0;
+    for (auto &h : t->hdr) maxblk = std::max(maxblk, h.size);
+    if (tile_vars != 64 && tile_vars != 128 && tile_vars != 256 && tile_vars != 512) {
+        *err = "tile_vars must be 64, 128, 256 or 512";
+        return HEOM_E_INVAL;
     }
-    t->tiles.push_back((uint32_t)np);
+    if ((uint32_t)tile_vars < maxblk) {
+        *err = "tile_vars is smaller than the largest pattern block";
+        return HEOM_E_INVAL;
+    }
+    t->tile_vars = tile_vars;
+    t->tiles.clear();
+    const size_t np = t->hdr.size();
+    size_t i = 0;
+    t->max_np = t->max_nc = t->max_nk = 0;
+    while (i < np) {
+        TileRec r{};
+        r.p0 = (uint32_t)i;
+        r.v0 = t->hdr[i].off;
+        uint32_t acc = 0;
+        while (i < np && acc + t->hdr[i].size <= (uint32_t)tile_vars) acc += t->hdr[i++].size;
+        r.np = (uint32_t)i - r.p0;
+        r.nv = acc;
+        r.c0 = t->hdr[r.p0].cat_base;
+        r.nc = (i < np ? t->hdr[i].cat_base : (uint32_t)t->cat.size()) - r.c0;
+        r.k0 = t->hdr[r.p0].conn_base;
+        r.nk = (i < np ? t->hdr[i].conn_base : (uint32_t)t->conn.size()) - r.k0;
+        t->max_np = std::max(t->max_np, r.np);
+        t->max_nc = std::max(t->max_nc, r.nc);
+        t->max_nk = std::max(t->max_nk, r.nk);
+        t->tiles.push_back(r);
+    }
+    t->top_tile = (uint32_t)t->tiles.size();
+    for (size_t k = 0; k < t->tiles.size(); ++k)
+        if (t->hdr[t->tiles[k].p0].tier == t->L) { t->top_tile = (uint32_t)k; break; }
+    // LDS per workgroup: values, pattern headers, categories, connections
+    t->lds_bytes = 16u * tile_vars + 32u * t->max_np + 16u * t->max_nc + 8u * t->max_nk +
+                   16u * (uint32_t)t->m * (uint32_t)(t->L + 1);
+    if (t->lds_bytes > 64u * 1024u) {
+        *err = "tile needs more than 64 KiB of LDS";
+        return HEOM_E_UNSUPPORTED;
+    }
     t->uploaded = false;
     pack_image(t);
     return HEOM_OK;
@@ -447,21 +489,25 @@ void pack_image(HostTables *t) {
     ip.d = t->d;
     ip.n_pat = (int32_t)t->hdr.size();
     ip.n_var = t->n_var;
-    ip.n_tiles = (uint32_t)(t->tiles.size() - 1);
+    ip.n_tiles = (uint32_t)t->tiles.size();
     ip.tile_vars = (uint32_t)t->tile_vars;
+    ip.max_np = t->max_np;
+    ip.max_nc = t->max_nc;
+    ip.max_nk = t->max_nk;
+    ip.lds_bytes = t->lds_bytes;
     size_t o = align256(sizeof(InstParams));
     ip.off_lut = o;   o = align256(o + t->lut.size() * sizeof(double));
     ip.off_hdr = o;   o = align256(o + t->hdr.size() * sizeof(PatHdr));
     ip.off_cat = o;   o = align256(o + t->cat.size() * sizeof(CatRec));
     ip.off_conn = o;  o = align256(o + t->conn.size() * sizeof(Conn));
-    ip.off_tile = o;  o = align256(o + t->tiles.size() * sizeof(uint32_t));
+    ip.off_tile = o;  o = align256(o + t->tiles.size() * sizeof(TileRec));
     t->image.assign(o, 0);
     std::memcpy(t->image.data(), &ip, sizeof ip);
     std::memcpy(t->image.data() + ip.off_lut, t->lut.data(), t->lut.size() * sizeof(double));
     std::memcpy(t->image.data() + ip.off_hdr, t->hdr.data(), t->hdr.size() * sizeof(PatHdr));
     std::memcpy(t->image.data() + ip.off_cat, t->cat.data(), t->cat.size() * sizeof(CatRec));
     std::memcpy(t->image.data() + ip.off_conn, t->conn.data(), t->conn.size() * sizeof(Conn));
-    std::memcpy(t->image.data() + ip.off_tile, t->tiles.data(), t->tiles.size() * sizeof(uint32_t));
+    std::memcpy(t->image.data() + ip.off_tile, t->tiles.data(), t->tiles.size() * sizeof(TileRec));
 }
 
 }  // namespace heom

@@ -22,12 +22,13 @@ HEOM_NOBS = 10
 HEOM_FP64 = 0
 HEOM_FP32 = 1
 ERRORS = {-1: "E_INVAL", -2: "E_NOMEM", -3: "E_TOO_LARGE", -4: "E_HIP", -5: "E_NONFINITE",
-          -6: "E_UNSUPPORTED", -7: "E_STATE"}
+          -6: "E_UNSUPPORTED", -7: "E_STATE", -8: "E_TIMEOUT"}
 
 # every symbol include/heom.h declares
 SYMBOLS = ["heom_build_tables", "heom_set_params", "heom_table_info", "heom_upload", "heom_tier0_pure",
            "heom_init_state", "heom_rhs", "heom_propagate", "heom_observables", "heom_export_layout",
-           "heom_export_coefficients", "heom_free_tables", "heom_last_error", "heom_version"]
+           "heom_export_coefficients", "heom_free_tables", "heom_last_error", "heom_version",
+           "heom_set_tuning", "heom_get_tuning", "heom_work_status"]
 
 
 class HeomError(RuntimeError):
@@ -43,6 +44,12 @@ class _Problem(ctypes.Structure):
                 ("nu", ctypes.POINTER(ctypes.c_double)),
                 ("eps", ctypes.c_double), ("omega_c", ctypes.c_double), ("g", ctypes.c_double),
                 ("kappa", ctypes.c_double), ("terminator", ctypes.c_double)]
+
+
+class _Tuning(ctypes.Structure):
+    _fields_ = [("tile_vars", ctypes.c_int32), ("persistent", ctypes.c_int32), ("xcd_map", ctypes.c_int32),
+                ("max_workgroups", ctypes.c_int32), ("spin_limit", ctypes.c_int32),
+                ("cache_policy", ctypes.c_int32)]
 
 
 class _Sizes(ctypes.Structure):
@@ -71,6 +78,9 @@ def _load():
         "heom_observables": [vp, vp, vp, vp],
         "heom_export_layout": [vp, ctypes.POINTER(i64), ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)],
         "heom_export_coefficients": [vp, dp, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)],
+        "heom_set_tuning": [vp, ctypes.POINTER(_Tuning)],
+        "heom_get_tuning": [vp, ctypes.POINTER(_Tuning)],
+        "heom_work_status": [vp, vp, ctypes.c_size_t, vp],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -188,6 +198,41 @@ class Tables:
 
     def observables(self, y, obs, stream=None):
         _check(LIB.heom_observables(self._h, _ptr(y), _ptr(obs), _stream(stream)))
+
+    def tuning(self) -> dict:
+        z = _Tuning()
+        _check(LIB.heom_get_tuning(self._h, ctypes.byref(z)))
+        return {name: getattr(z, name) for name, _ in _Tuning._fields_}
+
+    def set_tuning(self, **kw):
+        """Change launch knobs (tile_vars, persistent, xcd_map, max_workgroups,
+        spin_limit). A new tile_vars needs a new upload()."""
+        cur = self.tuning()
+        cur["tile_vars"] = 0
+        cur.update(kw)
+        z = _Tuning(**cur)
+        _check(LIB.heom_set_tuning(self._h, ctypes.byref(z)))
+
+    def max_block(self) -> int:
+        """Largest pattern block (unique variables), the smallest allowed tile."""
+        lay = self.export_layout()
+        n_pat, m = int(lay[0]), int(lay[2])
+        pos, best = 4, 0
+        for _ in range(n_pat):
+            G = int(lay[pos + 1])
+            h = 0
+            for q in range(G):
+                mult = int(lay[pos + 3 + q * (2 + m) + 1])
+                h += mult >= 2
+            best = max(best, (G + 1) ** 2 + h)
+            pos += 3 + G * (2 + m)
+        return best
+
+    def work_status(self, work, stream=None):
+        """Synchronize and raise HeomError(E_TIMEOUT) if a persistent launch
+        that used `work` gave up at a grid barrier."""
+        wbytes = work.numel() * work.element_size()
+        _check(LIB.heom_work_status(self._h, _ptr(work), wbytes, _stream(stream)))
 
     def export_layout(self) -> np.ndarray:
         need = ctypes.c_size_t()

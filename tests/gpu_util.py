@@ -32,7 +32,8 @@ def gpu_rhs(T, torch, y: np.ndarray) -> np.ndarray:
     return dy.cpu().numpy()
 
 
-def gpu_propagate(T, torch, tier0: np.ndarray, dt: float, steps: int, every: int, precision: int = 0):
+def gpu_propagate(T, torch, tier0: np.ndarray, dt: float, steps: int, every: int, precision: int = 0,
+                  check_status: bool = True):
     info = T.info()
     s = torch.cuda.current_stream()
     y = torch.empty(info["n_var"], dtype=torch.complex128, device="cuda")
@@ -42,6 +43,8 @@ def gpu_propagate(T, torch, tier0: np.ndarray, dt: float, steps: int, every: int
     nobs = steps // every + 1 if every > 0 else 0
     obs = torch.zeros(max(nobs, 1) * 10, dtype=torch.float64, device="cuda")
     T.propagate(y, work, dt, steps, every, obs if every > 0 else None, precision, s)
+    if check_status:
+        T.work_status(work, s)        # raises if a grid barrier timed out
     torch.cuda.synchronize()
     return y.cpu().numpy(), obs.cpu().numpy().reshape(-1, 10)[:nobs]
 

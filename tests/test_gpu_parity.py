@@ -208,3 +208,79 @@ def test_propagate_zero_steps_and_determinism():
     a, oa = gpu_propagate(T, torch, t0, 0.02, 500, 50)
     b, ob = gpu_propagate(T, torch, t0, 0.02, 500, 50)
     assert np.array_equal(a, b) and np.array_equal(oa, ob)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_persistent_equals_stage_launches(precision):
+    for name, steps in (("localized", 200), ("saturated", 30)):
+        p = W.WORKLOADS[name]()
+        T, torch = upload(p)
+        state = "site1" if name == "localized" else "upper_polariton"
+        t0 = named_tier0(T, p, state)
+        T.set_tuning(persistent=1)
+        a, oa = gpu_propagate(T, torch, t0, 0.02, steps, 10, precision)
+        T.set_tuning(persistent=0)
+        b, ob = gpu_propagate(T, torch, t0, 0.02, steps, 10, precision)
+        assert np.array_equal(a, b) and np.array_equal(oa, ob), name
+
+
+def test_tiling_and_mapping_variants_identical():
+    p = W.config_localized()
+    T, torch = upload(p)
+    t0 = named_tier0(T, p, "site1")
+    ref, oref = gpu_propagate(T, torch, t0, 0.02, 100, 10)
+    for tv in (64, 128, 256, 512):
+        for xcd in (0, 1):
+            for pers in (0, 1):
+                T.set_tuning(tile_vars=tv, xcd_map=xcd, persistent=pers, cache_policy=(tv // 64) % 8)
+                buf = torch.empty(T.info()["table_bytes"], dtype=torch.uint8, device="cuda")
+                T.upload(buf, torch.cuda.current_stream())
+                y, o = gpu_propagate(T, torch, t0, 0.02, 100, 10)
+                assert np.array_equal(y, ref) and np.array_equal(o, oref), (tv, xcd, pers)
+
+
+def test_split_top_tier_launch_identical():
+    # >= 2048 tiles: each stage runs as two launches (lower tiers, top tier)
+    p = W.config_saturated()
+    T, torch = upload(p)
+    T.set_tuning(tile_vars=64)
+    buf = torch.empty(T.info()["table_bytes"], dtype=torch.uint8, device="cuda")
+    T.upload(buf, torch.cuda.current_stream())
+    assert T.info()["n_tiles"] >= 2048
+    S = uvar.UVarSystem(p)
+    A = S.generator()
+    y = W.random_vector(S.n_var, 3)
+    got = gpu_rhs(T, torch, y)
+    assert np.all(np.abs(got - A @ y) <= rhs_bound(A, y))
+    t0 = named_tier0(T, p, "upper_polariton")
+    a, oa = gpu_propagate(T, torch, t0, 0.02, 20, 5)
+    T.set_tuning(tile_vars=256)
+    buf = torch.empty(T.info()["table_bytes"], dtype=torch.uint8, device="cuda")
+    T.upload(buf, torch.cuda.current_stream())
+    b, ob = gpu_propagate(T, torch, t0, 0.02, 20, 5)
+    assert np.array_equal(a, b) and np.array_equal(oa, ob)
+
+
+def test_persistent_few_workgroups_many_tiles():
+    # workgroups that own several tiles each restage metadata per tile
+    p = W.config_saturated()
+    T, torch = upload(p)
+    t0 = named_tier0(T, p, "upper_polariton")
+    T.set_tuning(persistent=0)
+    ref, oref = gpu_propagate(T, torch, t0, 0.02, 20, 5)
+    T.set_tuning(persistent=1, max_workgroups=37)
+    y, o = gpu_propagate(T, torch, t0, 0.02, 20, 5)
+    assert np.array_equal(y, ref) and np.array_equal(o, oref)
+
+
+def test_barrier_timeout_is_reported():
+    from paper_2608_20657_amd import heom
+    p = W.config_localized()
+    T, torch = upload(p)
+    t0 = named_tier0(T, p, "site1")
+    T.set_tuning(persistent=1, spin_limit=1)      # barriers give up almost at once
+    with pytest.raises(heom.HeomError) as e:
+        gpu_propagate(T, torch, t0, 0.02, 50, 10)
+    assert e.value.code == -8
+    T.set_tuning(spin_limit=0)
+    gpu_propagate(T, torch, t0, 0.02, 50, 10)     # the flag is cleared per launch
