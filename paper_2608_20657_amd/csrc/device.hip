@@ -45,7 +45,7 @@ struct Dev {
     const double *lut;
     const PatHdr *hdr;
     const CatRec *cat;
-    const Conn *conn;
+    const uint32_t *gidx;
     const TileRec *tiles;
 };
 
@@ -57,7 +57,7 @@ Dev dev_view(const HostTables &t) {
     D.lut = reinterpret_cast<const double *>(b + ip->off_lut);
     D.hdr = reinterpret_cast<const PatHdr *>(b + ip->off_hdr);
     D.cat = reinterpret_cast<const CatRec *>(b + ip->off_cat);
-    D.conn = reinterpret_cast<const Conn *>(b + ip->off_conn);
+    D.gidx = reinterpret_cast<const uint32_t *>(b + ip->off_gidx);
     D.tiles = reinterpret_cast<const TileRec *>(b + ip->off_tile);
     return D;
 }
@@ -106,18 +106,6 @@ __device__ __forceinline__ uint32_t xcd_tile(uint32_t b, uint32_t n) {
     const uint32_t X = 8;
     uint32_t q = n / X, rem = n % X, x = b % X, idx = b / X;
     return x < rem ? x * (q + 1) + idx : rem * (q + 1) + (x - rem) * q + idx;
-}
-
-// Index of the target variable <a'|R'|b'> for a connection record; a', b'
-// are target categories (-1 = cavity), `same` = same molecule.
-__device__ __forceinline__ uint32_t tgt_index(Conn cr, int a, int b, bool same) {
-    const uint32_t G1 = conn_G(cr.info) + 1;
-    if (a < 0 && b < 0) return cr.off;
-    if (b < 0) return cr.off + (uint32_t)(a + 1) * G1;
-    if (a < 0) return cr.off + (uint32_t)(b + 1);
-    if (same) return cr.off + (uint32_t)(a + 1) * (G1 + 1);
-    if (a == b) return cr.off + G1 * G1 + __popc(conn_tmask(cr.info) & ((1u << a) - 1u));
-    return cr.off + (uint32_t)(a + 1) * G1 + (uint32_t)(b + 1);
 }
 
 __device__ __forceinline__ uint32_t vbyte(uint64_t v, int k) { return (uint32_t)(v >> (8 * k)) & 0xffu; }
@@ -216,7 +204,7 @@ struct Smem {
     double2 *val;
     PatHdr *hdr;
     CatRec *cat;
-    Conn *con;
+    uint32_t *gix;
     double *lut;
 };
 
@@ -225,15 +213,34 @@ __device__ __forceinline__ Smem carve(unsigned char *smem, const InstParams &P) 
     S.val = reinterpret_cast<double2 *>(smem);
     S.hdr = reinterpret_cast<PatHdr *>(smem + 16u * P.tile_vars);
     S.cat = reinterpret_cast<CatRec *>(S.hdr + P.max_np);
-    S.con = reinterpret_cast<Conn *>(S.cat + P.max_nc);
-    S.lut = reinterpret_cast<double *>(S.con + P.max_nk);
+    S.gix = reinterpret_cast<uint32_t *>(S.cat + P.max_nc);
+    S.lut = reinterpret_cast<double *>(S.gix + ((P.max_ng + 3u) & ~3u));
     return S;
 }
 
 __device__ __forceinline__ void stage_meta(const Dev &D, const TileRec &TR, const Smem &S) {
     stage_copy(S.hdr, D.hdr + TR.p0, TR.np);
     stage_copy(S.cat, D.cat + TR.c0, TR.nc);
-    stage_copy(S.con, D.conn + TR.k0, TR.nk);
+    const uint32_t *g = D.gidx + TR.g0;
+    for (uint32_t i = threadIdx.x; i < TR.ng; i += blockDim.x) S.gix[i] = g[i];
+}
+
+// Exclusive prefix sum of x over the threads of the workgroup (thread order).
+__device__ __forceinline__ uint32_t wg_exclusive_scan(uint32_t x) {
+    __shared__ uint32_t wsum[MAX_TILE / 64];
+    const uint32_t lane = threadIdx.x & 63u, wid = threadIdx.x >> 6;
+    uint32_t v = x;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t y = __shfl_up(v, d, 64);
+        if (lane >= (uint32_t)d) v += y;
+    }
+    if (lane == 63u) wsum[wid] = v;
+    __syncthreads();
+    uint32_t base = 0;
+    for (uint32_t w = 0; w < wid; ++w) base += wsum[w];
+    __syncthreads();
+    return base + v - x;
 }
 
 __device__ __forceinline__ void stage_lut(const Dev &D, const InstParams &P, double *lut) {
@@ -280,8 +287,7 @@ __device__ __forceinline__ void process_tile(const InstParams &P, const TileRec 
                                              const StageArgs &a, bool first_tile) {
     const uint32_t t = threadIdx.x;
     const bool active = t < TR.nv;
-    enum { TZ = 0, TX = 1, TY = 2, TP = 3, TS = 4 };
-    int kind = TZ, A = 0, B = 0, q = 0, r = 0;
+    int kind = KIND_Z, A = 0, B = 0, q = 0, r = 0;
     uint32_t base = 0, lo = 0;
     PatHdr H{};
     CatRec cq{}, cr2{};
@@ -289,7 +295,8 @@ __device__ __forceinline__ void process_tile(const InstParams &P, const TileRec 
     uint32_t idx[4 * M];
     uint32_t live = 0;
     double2 v[4 * M];
-    double2 own = make_double2(0.0, 0.0);
+    double2 own = make_double2(0.0, 0.0), ybv = make_double2(0.0, 0.0);
+    float2 ex = make_float2(0.0f, 0.0f);
     if (active) {
         uint32_t hi = TR.np;  // block lo holds variable t
         while (hi - lo > 1) {
@@ -310,47 +317,32 @@ __device__ __forceinline__ void process_tile(const InstParams &P, const TileRec 
             A = B = __ffs(mask);  // category index + 1
             isT = true;
         }
-        kind = (A == 0 && B == 0) ? TZ : (B == 0 ? TX : (A == 0 ? TY : ((A == B && !isT) ? TP : TS)));
+        kind = (A == 0 && B == 0) ? KIND_Z : (B == 0 ? KIND_X : (A == 0 ? KIND_Y : ((A == B && !isT) ? KIND_P : KIND_S)));
         q = A - 1;
         r = B - 1;
         chi = TOP ? false : (H.tier < P.L);   // the top tier has no up moves
         const CatRec *cats = S.cat + (H.cat_base - TR.c0);
-        const Conn *cons = S.con + (H.conn_base - TR.k0);
         if (A > 0) cq = cats[q];
         if (B > 0) cr2 = cats[r];
-        const bool rowmv = (kind == TX || kind == TP || kind == TS);
-        const bool colmv = (kind == TY || kind == TS);
+        live = live_slots(kind, chi, cq.vec, cr2.vec, M);
+    }
+    // position of this variable's gather indices in the tile's list
+    const uint32_t goff = wg_exclusive_scan(__popc(live));
+    if (active) {
 #pragma unroll
-        for (int k = 0; k < M; ++k) {
-            const uint32_t nq = vbyte(cq.vec, k), nr = vbyte(cr2.vec, k);
-            uint32_t dq = cq.conn_off + (chi ? M : 0), dr = cr2.conn_off + (chi ? M : 0);
-            for (int j = 0; j < k; ++j) {
-                dq += vbyte(cq.vec, j) != 0;
-                dr += vbyte(cr2.vec, j) != 0;
-            }
-            const bool l0 = rowmv && kind != TP && chi, l1 = rowmv && nq;
-            const bool l2 = colmv && chi, l3 = colmv && nr;
-            const Conn c0 = l0 ? cons[cq.conn_off + k] : Conn{0u, 0u};
-            const Conn c1 = l1 ? cons[dq] : Conn{0u, 0u};
-            const Conn c2 = l2 ? cons[cr2.conn_off + k] : Conn{0u, 0u};
-            const Conn c3 = l3 ? cons[dr] : Conn{0u, 0u};
-            // row moves: target row = q' of the moved molecule, column = the
-            // column molecule's category in the target (cavity for X)
-            const int q0 = (int)conn_q(c0.info), q1 = (int)conn_q(c1.info);
-            const int q2 = (int)conn_q(c2.info), q3 = (int)conn_q(c3.info);
-            idx[k] = l0 ? tgt_index(c0, q0, kind == TX ? -1 : conn_remap(c0.info, q, r), false) : 0u;
-            idx[M + k] = l1 ? (kind == TP ? tgt_index(c1, q1, q1, true)
-                                          : tgt_index(c1, q1, kind == TX ? -1 : conn_remap(c1.info, q, r), false))
-                            : 0u;
-            idx[2 * M + k] = l2 ? tgt_index(c2, kind == TY ? -1 : conn_remap(c2.info, r, q), q2, false) : 0u;
-            idx[3 * M + k] = l3 ? tgt_index(c3, kind == TY ? -1 : conn_remap(c3.info, r, q), q3, false) : 0u;
-            live |= ((uint32_t)l0 << k) | ((uint32_t)l1 << (M + k)) | ((uint32_t)l2 << (2 * M + k)) |
-                    ((uint32_t)l3 << (3 * M + k));
+        for (int j = 0; j < 4 * M; ++j) {
+            const bool up_slot = ((j / M) & 1) == 0;   // slots 0..M-1 and 2M..3M-1 are up moves
+            idx[j] = (!(TOP && up_slot) && ((live >> j) & 1u)) ? S.gix[goff + __popc(live & ((1u << j) - 1u))] : 0u;
         }
         own = load_own<HAS64, HAS32>(a, TR.v0 + t);
+        // the base vector and the extra term only depend on t: issue them now
+        if (BASE == BASE_Y) ybv = (a.policy & 2u) ? ld_stream(a.ybase + TR.v0 + t) : a.ybase[TR.v0 + t];
+        if (EXTRA) ex = a.extra[TR.v0 + t];
 #pragma unroll
-        for (int j = 0; j < 4 * M; ++j)
-            v[j] = ((live >> j) & 1u) ? load_in<HAS64, HAS32>(a, idx[j]) : make_double2(0.0, 0.0);
+        for (int j = 0; j < 4 * M; ++j) {
+            const bool up_slot = ((j / M) & 1) == 0;
+            v[j] = (!(TOP && up_slot) && ((live >> j) & 1u)) ? load_in<HAS64, HAS32>(a, idx[j]) : make_double2(0.0, 0.0);
+        }
         S.val[t] = own;
     }
     __syncthreads();
@@ -372,15 +364,15 @@ __device__ __forceinline__ void process_tile(const InstParams &P, const TileRec 
 #pragma unroll
         for (int k = 0; k < M; ++k) gam += P.nu[k] * (double)vbyte(H.cnt, k);
         double2 acc, hsum;  // hsum: Hamiltonian bracket, multiplied by -i g below
-        if (kind == TZ) {
+        if (kind == KIND_Z) {
             // Z: -i g sum_q M_q (X_q - Y_q) - (Gamma + kappa) Z   (Eq. HZ)
             hsum = make_double2(0, 0);
             for (int c = 0; c < G; ++c) hsum = cadd(hsum, cscale(mult(c), csub(sv(c + 1, 0), sv(0, c + 1))));
             acc = cscale(-(gam + P.kappa), own);
-        } else if (kind == TX || kind == TY) {
+        } else if (kind == KIND_X || kind == KIND_Y) {
             // X_q: -i delta X - i g (Z - R_q) - (Gamma + kappa/2 + Delta) X   (Eq. HX)
             // Y_q: +i delta Y - i g (C_q - Z) - (Gamma + kappa/2 + Delta) Y
-            const bool isX = kind == TX;
+            const bool isX = kind == KIND_X;
             const int c = isX ? q : r;
             double2 R = sv(c + 1, c + 1);
             if ((H.tmask >> c) & 1u) R = cadd(R, cscale(mult(c) - 1.0, svT(c)));
@@ -390,7 +382,7 @@ __device__ __forceinline__ void process_tile(const InstParams &P, const TileRec 
             const double re = -(gam + 0.5 * P.kappa + P.term);
             const double dl = isX ? P.delta : -P.delta;
             acc = make_double2(re * own.x + dl * own.y, re * own.y - dl * own.x);
-        } else if (kind == TP) {
+        } else if (kind == KIND_P) {
             // P_q: -i g (Y_q - X_q) - Gamma P
             hsum = csub(sv(0, A), sv(A, 0));
             acc = cscale(-gam, own);
@@ -406,8 +398,8 @@ __device__ __forceinline__ void process_tile(const InstParams &P, const TileRec 
             const uint32_t nq = vbyte(cq.vec, k), nr = vbyte(cr2.vec, k);
             const double uq = up[k * L1 + nq], dq = dn[k * L1 + nq];
             const double ur = up[k * L1 + nr], dr = dn[k * L1 + nr];
-            const double cre = kind == TP ? P.cr[k] - P.ccr[k] : P.cr[k];
-            const double cim = kind == TP ? P.ci[k] - P.cci[k] : P.ci[k];
+            const double cre = kind == KIND_P ? P.cr[k] - P.ccr[k] : P.cr[k];
+            const double cim = kind == KIND_P ? P.ci[k] - P.cci[k] : P.ci[k];
             cfma(acc, make_double2(0.0, -uq), v[k]);
             cfma(acc, make_double2(dq * cim, -dq * cre), v[M + k]);
             cfma(acc, make_double2(0.0, ur), v[2 * M + k]);
@@ -416,13 +408,12 @@ __device__ __forceinline__ void process_tile(const InstParams &P, const TileRec 
         acc.x += P.g * hsum.y;
         acc.y -= P.g * hsum.x;
         if (EXTRA) {
-            const float2 e = a.extra[TR.v0 + t];
-            acc.x += a.extra_scale * (double)e.x;
-            acc.y += a.extra_scale * (double)e.y;
+            acc.x += a.extra_scale * (double)ex.x;
+            acc.y += a.extra_scale * (double)ex.y;
         }
         res = cscale(a.alpha, acc);
         if (BASE == BASE_IN) res = cadd(res, own);
-        if (BASE == BASE_Y) res = cadd(res, (a.policy & 2u) ? ld_stream(a.ybase + TR.v0 + t) : a.ybase[TR.v0 + t]);
+        if (BASE == BASE_Y) res = cadd(res, ybv);
         if (a.policy & 4u) {
             if (OUT64) st_stream(a.out64 + TR.v0 + t, res);
             else st_stream(a.out32 + TR.v0 + t, res);

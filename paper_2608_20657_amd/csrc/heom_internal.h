@@ -74,13 +74,30 @@ HEOM_HD int conn_remap(uint32_t info, int q, int r) {
 }
 
 // One workgroup tile: a run of whole patterns and the contiguous ranges of
-// their variables, categories and connection records. 32 bytes.
+// their variables, categories and hierarchy gather indices. 32 bytes.
 struct TileRec {
     uint32_t p0, np;     // patterns
     uint32_t v0, nv;     // unique variables
     uint32_t c0, nc;     // category records
-    uint32_t k0, nk;     // connection records
+    uint32_t g0, ng;     // gather indices (see expand_gathers)
 };
+
+// Hierarchy gather slots of one unique variable (Eqs. uvar-up, uvar-down):
+// for each channel k the row molecule raised (slot k), lowered (M+k), the
+// column molecule raised (2M+k), lowered (3M+k). A variable's live slots,
+// in slot order, each hold the index of the target variable they read.
+enum { KIND_Z = 0, KIND_X = 1, KIND_Y = 2, KIND_P = 3, KIND_S = 4 };
+HEOM_HD uint32_t live_slots(int kind, bool chi, uint64_t vq, uint64_t vr, int M) {
+    const bool rowmv = kind == KIND_X || kind == KIND_P || kind == KIND_S;
+    const bool colmv = kind == KIND_Y || kind == KIND_S;
+    uint32_t live = 0;
+    for (int k = 0; k < M; ++k) {
+        const bool nq = ((vq >> (8 * k)) & 0xffu) != 0, nr = ((vr >> (8 * k)) & 0xffu) != 0;
+        live |= ((uint32_t)(rowmv && kind != KIND_P && chi) << k) | ((uint32_t)(rowmv && nq) << (M + k)) |
+                ((uint32_t)(colmv && chi) << (2 * M + k)) | ((uint32_t)(colmv && nr) << (3 * M + k));
+    }
+    return live;
+}
 static_assert(sizeof(TileRec) == 32, "TileRec layout");
 
 // Per-instance numeric parameters (device image header). 256-byte aligned.
@@ -97,9 +114,9 @@ struct InstParams {
     double cr[HEOM_MAX_M], ci[HEOM_MAX_M];      // c_k
     double ccr[HEOM_MAX_M], cci[HEOM_MAX_M];    // c_check_k
     int32_t m, L, d, n_pat;
-    uint32_t n_var, n_tiles, tile_vars, max_np, max_nc, max_nk, lds_bytes, pad;
+    uint32_t n_var, n_tiles, tile_vars, max_np, max_nc, max_ng, lds_bytes, pad;
     // byte offsets of the sections from the image base
-    uint64_t off_lut, off_hdr, off_cat, off_conn, off_tile;
+    uint64_t off_lut, off_hdr, off_cat, off_gidx, off_tile;
 };
 
 struct HostTables {
@@ -116,7 +133,8 @@ struct HostTables {
     std::vector<Conn> conn;
     std::vector<uint32_t> conn_target;  // target pattern index per Conn
     std::vector<TileRec> tiles;         // workgroup tiles
-    uint32_t max_np = 0, max_nc = 0, max_nk = 0, lds_bytes = 0;
+    std::vector<uint32_t> gidx;         // per-tile lists of gather target indices
+    uint32_t max_np = 0, max_nc = 0, max_ng = 0, lds_bytes = 0;
     std::vector<uint16_t> pat_ids;      // flat: d dist ids + pool ids
     std::vector<uint32_t> pat_start;    // per pattern start in pat_ids, then end
     uint32_t n_var = 0;
@@ -135,6 +153,7 @@ struct HostTables {
 int build(const heom_problem *p, HostTables *t, std::string *err);
 int set_params(HostTables *t, const heom_problem *p, std::string *err);
 int make_tiles(HostTables *t, int tile_vars, std::string *err);
+void expand_gathers(const HostTables &t, uint32_t p, std::vector<uint32_t> *out);
 void pack_image(HostTables *t);
 size_t tier0_size(const HostTables &t);
 

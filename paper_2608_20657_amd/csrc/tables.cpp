@@ -398,6 +398,75 @@ int build(const heom_problem *p, HostTables *t, std::string *err) {
     return HEOM_OK;
 }
 
+// Index of the target variable <a'|R'|b'> of a connection record; a', b'
+// are target categories (-1 = cavity), `same` = same molecule.
+static uint32_t tgt_index(const Conn &cr, int a, int b, bool same) {
+    const uint32_t G1 = conn_G(cr.info) + 1;
+    if (a < 0 && b < 0) return cr.off;
+    if (b < 0) return cr.off + (uint32_t)(a + 1) * G1;
+    if (a < 0) return cr.off + (uint32_t)(b + 1);
+    if (same) return cr.off + (uint32_t)(a + 1) * (G1 + 1);
+    if (a == b) return cr.off + G1 * G1 + (uint32_t)__builtin_popcount(conn_tmask(cr.info) & ((1u << a) - 1u));
+    return cr.off + (uint32_t)(a + 1) * G1 + (uint32_t)(b + 1);
+}
+
+// Append, for every unique variable of pattern p in layout order, the target
+// indices of its live hierarchy gathers in slot order (see live_slots). The
+// target of a move of one molecule of category q by +-e_k is read through
+// the connection record of (q, k, direction): the moved molecule lies in q'
+// of the target, an unmoved molecule of category r in conn_remap(q, r).
+void expand_gathers(const HostTables &t, uint32_t p, std::vector<uint32_t> *out) {
+    const PatHdr &H = t.hdr[p];
+    const int G = H.G, G1 = G + 1, M = t.m;
+    const bool chi = H.tier < t.L;
+    const CatRec *cats = &t.cat[H.cat_base];
+    const Conn *cons = &t.conn[H.conn_base];
+    auto rup = [&](const CatRec &c, int k) { return cons[c.conn_off + k]; };
+    auto rdn = [&](const CatRec &c, int k) {
+        uint32_t r = c.conn_off + (chi ? M : 0);
+        for (int j = 0; j < k; ++j) r += vcomp(c.vec, j) != 0;
+        return cons[r];
+    };
+    for (uint32_t loc = 0; loc < H.size; ++loc) {
+        int A, B;
+        bool isT = false;
+        if (loc < (uint32_t)(G1 * G1)) {
+            A = (int)loc / G1;
+            B = (int)loc - A * G1;
+        } else {
+            uint32_t mask = H.tmask;
+            for (int s = (int)loc - G1 * G1; s > 0; --s) mask &= mask - 1u;
+            A = B = __builtin_ffs(mask);
+            isT = true;
+        }
+        const int kind = (A == 0 && B == 0) ? KIND_Z : (B == 0 ? KIND_X : (A == 0 ? KIND_Y : ((A == B && !isT) ? KIND_P : KIND_S)));
+        const int q = A - 1, r = B - 1;
+        const CatRec cq = A > 0 ? cats[q] : CatRec{}, cr = B > 0 ? cats[r] : CatRec{};
+        const uint32_t live = live_slots(kind, chi, cq.vec, cr.vec, M);
+        for (int j = 0; j < 4 * M; ++j) {
+            if (!((live >> j) & 1u)) continue;
+            const int k = j % M, grp = j / M;
+            uint32_t idx;
+            if (grp == 0) {          // row molecule raised
+                const Conn c = rup(cq, k);
+                idx = tgt_index(c, (int)conn_q(c.info), kind == KIND_X ? -1 : conn_remap(c.info, q, r), false);
+            } else if (grp == 1) {   // row molecule lowered
+                const Conn c = rdn(cq, k);
+                const int qn = (int)conn_q(c.info);
+                idx = kind == KIND_P ? tgt_index(c, qn, qn, true)
+                                     : tgt_index(c, qn, kind == KIND_X ? -1 : conn_remap(c.info, q, r), false);
+            } else if (grp == 2) {   // column molecule raised
+                const Conn c = rup(cr, k);
+                idx = tgt_index(c, kind == KIND_Y ? -1 : conn_remap(c.info, r, q), (int)conn_q(c.info), false);
+            } else {                 // column molecule lowered
+                const Conn c = rdn(cr, k);
+                idx = tgt_index(c, kind == KIND_Y ? -1 : conn_remap(c.info, r, q), (int)conn_q(c.info), false);
+            }
+            out->push_back(idx);
+        }
+    }
+}
+
 int make_tiles(HostTables *t, int tile_vars, std::string *err) {
     uint32_t maxblk = 0;
     for (auto &h : t->hdr) maxblk = std::max(maxblk, h.size);
@@ -413,7 +482,8 @@ int make_tiles(HostTables *t, int tile_vars, std::string *err) {
     t->tiles.clear();
     const size_t np = t->hdr.size();
     size_t i = 0;
-    t->max_np = t->max_nc = t->max_nk = 0;
+    t->max_np = t->max_nc = t->max_ng = 0;
+    t->gidx.clear();
     while (i < np) {
         TileRec r{};
         r.p0 = (uint32_t)i;
@@ -424,18 +494,20 @@ int make_tiles(HostTables *t, int tile_vars, std::string *err) {
         r.nv = acc;
         r.c0 = t->hdr[r.p0].cat_base;
         r.nc = (i < np ? t->hdr[i].cat_base : (uint32_t)t->cat.size()) - r.c0;
-        r.k0 = t->hdr[r.p0].conn_base;
-        r.nk = (i < np ? t->hdr[i].conn_base : (uint32_t)t->conn.size()) - r.k0;
+        r.g0 = (uint32_t)t->gidx.size();
+        for (uint32_t p = r.p0; p < r.p0 + r.np; ++p) expand_gathers(*t, p, &t->gidx);
+        if (t->gidx.size() > 0xffffffffull) { *err = "more than 2^32-1 hierarchy gathers"; return HEOM_E_TOO_LARGE; }
+        r.ng = (uint32_t)t->gidx.size() - r.g0;
         t->max_np = std::max(t->max_np, r.np);
         t->max_nc = std::max(t->max_nc, r.nc);
-        t->max_nk = std::max(t->max_nk, r.nk);
+        t->max_ng = std::max(t->max_ng, r.ng);
         t->tiles.push_back(r);
     }
     t->top_tile = (uint32_t)t->tiles.size();
     for (size_t k = 0; k < t->tiles.size(); ++k)
         if (t->hdr[t->tiles[k].p0].tier == t->L) { t->top_tile = (uint32_t)k; break; }
     // LDS per workgroup: values, pattern headers, categories, connections
-    t->lds_bytes = 16u * tile_vars + 32u * t->max_np + 16u * t->max_nc + 8u * t->max_nk +
+    t->lds_bytes = 16u * tile_vars + 32u * t->max_np + 16u * t->max_nc + 4u * ((t->max_ng + 3u) & ~3u) +
                    16u * (uint32_t)t->m * (uint32_t)(t->L + 1);
     if (t->lds_bytes > 64u * 1024u) {
         *err = "tile needs more than 64 KiB of LDS";
@@ -493,20 +565,20 @@ void pack_image(HostTables *t) {
     ip.tile_vars = (uint32_t)t->tile_vars;
     ip.max_np = t->max_np;
     ip.max_nc = t->max_nc;
-    ip.max_nk = t->max_nk;
+    ip.max_ng = t->max_ng;
     ip.lds_bytes = t->lds_bytes;
     size_t o = align256(sizeof(InstParams));
     ip.off_lut = o;   o = align256(o + t->lut.size() * sizeof(double));
     ip.off_hdr = o;   o = align256(o + t->hdr.size() * sizeof(PatHdr));
     ip.off_cat = o;   o = align256(o + t->cat.size() * sizeof(CatRec));
-    ip.off_conn = o;  o = align256(o + t->conn.size() * sizeof(Conn));
+    ip.off_gidx = o;  o = align256(o + t->gidx.size() * sizeof(uint32_t));
     ip.off_tile = o;  o = align256(o + t->tiles.size() * sizeof(TileRec));
     t->image.assign(o, 0);
     std::memcpy(t->image.data(), &ip, sizeof ip);
     std::memcpy(t->image.data() + ip.off_lut, t->lut.data(), t->lut.size() * sizeof(double));
     std::memcpy(t->image.data() + ip.off_hdr, t->hdr.data(), t->hdr.size() * sizeof(PatHdr));
     std::memcpy(t->image.data() + ip.off_cat, t->cat.data(), t->cat.size() * sizeof(CatRec));
-    std::memcpy(t->image.data() + ip.off_conn, t->conn.data(), t->conn.size() * sizeof(Conn));
+    std::memcpy(t->image.data() + ip.off_gidx, t->gidx.data(), t->gidx.size() * sizeof(uint32_t));
     std::memcpy(t->image.data() + ip.off_tile, t->tiles.data(), t->tiles.size() * sizeof(TileRec));
 }
 
