@@ -224,6 +224,66 @@ int heom_work_status(const heom_tables *t, const void *work_dev, size_t work_byt
 /* Release a handle (NULL is allowed). Device memory is the caller's. */
 void heom_free_tables(heom_tables *t);
 
+/* ---------------------------------------------------------------------
+ * Many independent problems (the batched and served workloads).
+ *
+ * Problems with the same structure key (min(N, L+d+2), m, L, d) share one
+ * uploaded structure (Sec. V.C.4: beyond saturation only M_0 and the
+ * numeric parameters differ). Each problem then needs only a parameter
+ * block: heom_params_bytes bytes written by heom_upload_params.
+ * ------------------------------------------------------------------- */
+
+/* Bytes of one parameter block (scalars and coefficient look-up tables). */
+int heom_params_bytes(const heom_tables *t, size_t *bytes);
+
+/* Write the parameter block of `prob` on the structure of `t` into caller
+ * device memory `dev` (256-byte aligned, >= heom_params_bytes), synchronously
+ * on `stream`. Errors: E_INVAL if prob's structure key differs from t's. */
+int heom_upload_params(const heom_tables *t, const heom_problem *prob, void *dev, size_t bytes, void *stream);
+
+typedef struct heom_batch heom_batch;   /* opaque host handle */
+
+/* An empty batch with `capacity` slots. */
+int heom_batch_create(int32_t capacity, heom_batch **out);
+
+/* Put a problem into a slot (replacing what was there): its structure `t`
+ * (uploaded, kept alive and unmoved by the caller), its parameter block
+ * (NULL = the parameters uploaded with t), its state y_dev (t's layout,
+ * complex128, initialized e.g. by heom_init_state), a work buffer of at least
+ * work_bytes_fp64 bytes, its time step, and optionally an observable buffer
+ * of obs_capacity samples of HEOM_NOBS doubles: sample j holds the
+ * observables after j*obs_every steps of this slot (sample 0, the initial
+ * state, is the caller's, e.g. heom_observables). All pointers are caller
+ * device memory. The slot's step count restarts at 0. Takes effect at the
+ * next heom_batch_commit. */
+int heom_batch_set_slot(heom_batch *b, int32_t slot, const heom_tables *t, const void *params_dev, void *y_dev,
+                        void *work_dev, size_t work_bytes, double dt, double *obs_dev, int64_t obs_every,
+                        int64_t obs_capacity);
+
+/* Empty a slot (its buffers are no longer touched after the next commit). */
+int heom_batch_clear_slot(heom_batch *b, int32_t slot);
+
+/* Device bytes heom_batch_commit needs for the current slots. */
+int heom_batch_device_bytes(const heom_batch *b, size_t *bytes);
+
+/* Upload the slot records and the tile list (grouped by m) into caller
+ * device memory (256-byte aligned, >= heom_batch_device_bytes),
+ * synchronously on `stream`. Required after any set/clear. */
+int heom_batch_commit(heom_batch *b, void *dev, size_t bytes, void *stream);
+
+/* Advance every occupied slot by nsteps RK4 steps of its own dt (the same
+ * fused stages as heom_propagate; one launch per stage and per m covers the
+ * tiles of all slots). Each problem's trajectory is bitwise the same as with
+ * heom_propagate alone (no slot reads another slot's memory). precision as
+ * in heom_propagate. Errors: E_STATE if not committed since the last change. */
+int heom_batch_propagate(heom_batch *b, int64_t nsteps, int precision, void *stream);
+
+/* Steps a slot has taken since it was set. */
+int heom_batch_slot_steps(const heom_batch *b, int32_t slot, int64_t *steps);
+
+/* Release a batch handle (NULL is allowed). */
+void heom_batch_free(heom_batch *b);
+
 /* Message of the last failure on this thread ("" if none). */
 const char *heom_last_error(void);
 

@@ -24,6 +24,26 @@ struct heom_tables {
     HostTables t;
 };
 
+struct BatchSlotHost {
+    bool used = false;
+    const heom_tables *tables = nullptr;
+    const void *params = nullptr;
+    void *y = nullptr, *work = nullptr;
+    double dt = 0.0;
+    double *obs = nullptr;
+    int64_t obs_every = 0, obs_cap = 0, steps = 0;
+};
+
+struct heom_batch {
+    std::vector<BatchSlotHost> slots;
+    bool committed = false;
+    void *dev = nullptr;
+    size_t dev_bytes = 0;
+    int64_t steps_since_commit = 0;
+    uint32_t block = 64, lds = 0;
+    std::vector<std::pair<int, std::pair<uint32_t, uint32_t>>> groups;  // (m, (first tile, count))
+};
+
 namespace {
 
 thread_local std::string g_err;
@@ -582,6 +602,75 @@ __global__ __launch_bounds__(MAX_TILE) void persistent_kernel(Dev D, PersistArgs
     }
 }
 
+// ---------------------------------------------------------------- batches
+// One slot of a batch: an uploaded structure image, a params block (the
+// head of an image: InstParams + coefficient tables) and the slot's own
+// state, work and observable buffers.
+struct SlotRec {
+    const unsigned char *img;
+    const unsigned char *params;
+    double2 *y, *w0, *w1;     // FP64 stage vectors (FP32: w0 = second state buffer)
+    float2 *u1, *u2;          // FP32 increments
+    double *obs;
+    int64_t obs_every, obs_cap, step0;
+    double dt;
+};
+struct BatchTile {
+    uint32_t slot, tile;
+};
+
+// One RK4 stage of every tile of every slot in a tile list (all of one m).
+// Each variable is computed by the same arithmetic as in stage_kernel, so a
+// problem's trajectory does not depend on the other problems in the batch.
+template <int M, int PREC>
+__global__ __launch_bounds__(MAX_TILE) void batch_stage_kernel(const SlotRec *slots, const BatchTile *btiles, int s,
+                                                             int64_t steps_done, int64_t st, uint32_t policy) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const BatchTile B = btiles[blockIdx.x];
+    const SlotRec R = slots[B.slot];
+    const InstParams &P = *reinterpret_cast<const InstParams *>(R.params);
+    Dev D;
+    D.ip = &P;
+    D.lut = reinterpret_cast<const double *>(R.params + P.off_lut);
+    D.hdr = reinterpret_cast<const PatHdr *>(R.img + P.off_hdr);
+    D.cat = reinterpret_cast<const CatRec *>(R.img + P.off_cat);
+    D.gidx = reinterpret_cast<const uint32_t *>(R.img + P.off_gidx);
+    D.tiles = reinterpret_cast<const TileRec *>(R.img + P.off_tile);
+    const Smem S = carve(smem, P);
+    const TileRec TR = D.tiles[B.tile];
+    stage_meta(D, TR, S);
+    stage_lut(D, P, S.lut);
+    __syncthreads();
+    const double h = R.dt;
+    const int64_t gst = R.step0 + steps_done + st;   // steps of this slot so far, this one included
+    StageArgs a{};
+    a.policy = policy;
+    a.alpha = s == 0 ? h / 4.0 : (s == 1 ? h / 3.0 : (s == 2 ? h / 2.0 : h));
+    a.obs = (s == 3 && R.obs != nullptr && R.obs_every > 0 && gst % R.obs_every == 0 && gst / R.obs_every < R.obs_cap)
+                ? R.obs + (gst / R.obs_every) * HEOM_NOBS : nullptr;
+    const bool first = B.tile == 0;
+    if (PREC == HEOM_FP64) {
+        a.in64 = s == 0 ? R.y : (s == 2 ? R.w1 : R.w0);
+        a.ybase = R.y;
+        a.out64 = s == 3 ? R.y : (s == 1 ? R.w1 : R.w0);
+        if (s == 0) process_tile<M, true, false, BASE_IN, false, true, false>(P, TR, S, a, first);
+        else process_tile<M, true, false, BASE_Y, false, true, false>(P, TR, S, a, first);
+    } else {
+        // the state ping-pongs between y and w0 from the first step of the call
+        double2 *cur = ((st - 1) & 1) ? R.w0 : R.y, *nxt = ((st - 1) & 1) ? R.y : R.w0;
+        a.in64 = cur;
+        a.in32 = s == 1 ? R.u1 : (s == 2 ? R.u2 : R.u1);
+        a.extra = R.u1;
+        a.extra_scale = 4.0 / h;
+        a.ybase = cur;
+        a.out32 = s == 1 ? R.u2 : R.u1;
+        a.out64 = nxt;
+        if (s == 0) process_tile<M, true, false, BASE_NONE, false, false, false>(P, TR, S, a, false);
+        else if (s < 3) process_tile<M, false, true, BASE_NONE, true, false, false>(P, TR, S, a, false);
+        else process_tile<M, true, true, BASE_Y, false, true, false>(P, TR, S, a, first);
+    }
+}
+
 __global__ void observables_kernel(Dev D, const double2 *y, double *obs) {
     __shared__ double2 v[MAX_TILE];
     const uint32_t n0 = D.hdr[0].size;
@@ -693,6 +782,30 @@ int check_ready(const heom_tables *h) {
 int check_dev(const void *p, const char *name) {
     if (!p) return fail(HEOM_E_INVAL, std::string(name) + " is NULL");
     if (reinterpret_cast<uintptr_t>(p) % 16) return fail(HEOM_E_INVAL, std::string(name) + " is not 16-byte aligned");
+    return HEOM_OK;
+}
+
+template <int PREC>
+int batch_launch(const heom_batch *b, hipStream_t s, int stage, int64_t st, uint32_t policy) {
+    const SlotRec *recs = static_cast<const SlotRec *>(b->dev);
+    const size_t tile_off = (sizeof(SlotRec) * b->slots.size() + 255) & ~(size_t)255;
+    const BatchTile *tl = reinterpret_cast<const BatchTile *>(static_cast<const unsigned char *>(b->dev) + tile_off);
+    for (const auto &g : b->groups) {
+        const BatchTile *first = tl + g.second.first;
+        const dim3 grid(g.second.second), block(b->block);
+#define HEOM_BCASE(MM)                                                                                          \
+    case MM:                                                                                                    \
+        hipLaunchKernelGGL((batch_stage_kernel<MM, PREC>), grid, block, b->lds, s, recs, first, stage,        \
+                           b->steps_since_commit, st, policy);                                                  \
+        break;
+        switch (g.first) {
+            HEOM_BCASE(1) HEOM_BCASE(2) HEOM_BCASE(3) HEOM_BCASE(4)
+            HEOM_BCASE(5) HEOM_BCASE(6) HEOM_BCASE(7) HEOM_BCASE(8)
+            default: return fail(HEOM_E_UNSUPPORTED, "m out of range");
+        }
+#undef HEOM_BCASE
+        HIP_TRY(hipGetLastError());
+    }
     return HEOM_OK;
 }
 
@@ -1028,6 +1141,165 @@ int heom_export_coefficients(const heom_tables *h, double *out, size_t cap, size
 }
 
 void heom_free_tables(heom_tables *h) { delete h; }
+
+int heom_params_bytes(const heom_tables *h, size_t *bytes) {
+    if (!h || !bytes) return fail(HEOM_E_INVAL, "NULL argument");
+    const InstParams *ip = reinterpret_cast<const InstParams *>(h->t.image.data());
+    *bytes = ip->off_hdr;
+    return HEOM_OK;
+}
+
+int heom_upload_params(const heom_tables *h, const heom_problem *prob, void *dev, size_t bytes, void *stream) {
+    if (!h || !prob || !dev) return fail(HEOM_E_INVAL, "NULL argument");
+    if (reinterpret_cast<uintptr_t>(dev) % 256) return fail(HEOM_E_INVAL, "params buffer must be 256-byte aligned");
+    std::vector<unsigned char> blk;
+    std::string err;
+    if (int rc = pack_params(h->t, prob, &blk, &err)) return fail(rc, err);
+    if (bytes < blk.size()) return fail(HEOM_E_TOO_LARGE, "params buffer smaller than heom_params_bytes");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    HIP_TRY(hipMemcpyAsync(dev, blk.data(), blk.size(), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return HEOM_OK;
+}
+
+int heom_batch_create(int32_t capacity, heom_batch **out) {
+    if (!out || capacity < 1) return fail(HEOM_E_INVAL, "bad capacity or NULL out");
+    *out = nullptr;
+    heom_batch *b = new (std::nothrow) heom_batch;
+    if (!b) return fail(HEOM_E_NOMEM, "host allocation failed");
+    b->slots.resize((size_t)capacity);
+    *out = b;
+    return HEOM_OK;
+}
+
+int heom_batch_set_slot(heom_batch *b, int32_t slot, const heom_tables *t, const void *params_dev, void *y_dev,
+                        void *work_dev, size_t work_bytes, double dt, double *obs_dev, int64_t obs_every,
+                        int64_t obs_capacity) {
+    if (!b || slot < 0 || (size_t)slot >= b->slots.size()) return fail(HEOM_E_INVAL, "bad batch or slot");
+    if (int rc = check_ready(t)) return rc;
+    if (int rc = check_dev(y_dev, "y_dev")) return rc;
+    if (int rc = check_dev(work_dev, "work_dev")) return rc;
+    if (params_dev && reinterpret_cast<uintptr_t>(params_dev) % 256) return fail(HEOM_E_INVAL, "params_dev alignment");
+    if (work_bytes < work_bytes_for(t->t)) return fail(HEOM_E_TOO_LARGE, "work buffer smaller than work_bytes");
+    if (!std::isfinite(dt)) return fail(HEOM_E_INVAL, "dt not finite");
+    if (obs_every < 0 || obs_capacity < 0 || (obs_every > 0 && !obs_dev)) return fail(HEOM_E_INVAL, "bad observables");
+    BatchSlotHost &S = b->slots[(size_t)slot];
+    S.used = true;
+    S.tables = t;
+    S.params = params_dev ? params_dev : t->t.dev;
+    S.y = y_dev;
+    S.work = work_dev;
+    S.dt = dt;
+    S.obs = obs_dev;
+    S.obs_every = obs_every;
+    S.obs_cap = obs_capacity;
+    S.steps = 0;
+    b->committed = false;
+    return HEOM_OK;
+}
+
+int heom_batch_clear_slot(heom_batch *b, int32_t slot) {
+    if (!b || slot < 0 || (size_t)slot >= b->slots.size()) return fail(HEOM_E_INVAL, "bad batch or slot");
+    b->slots[(size_t)slot] = BatchSlotHost{};
+    b->committed = false;
+    return HEOM_OK;
+}
+
+int heom_batch_device_bytes(const heom_batch *b, size_t *bytes) {
+    if (!b || !bytes) return fail(HEOM_E_INVAL, "NULL argument");
+    size_t nt = 0;
+    for (const auto &S : b->slots)
+        if (S.used) nt += S.tables->t.tiles.size();
+    *bytes = ((sizeof(SlotRec) * b->slots.size() + 255) & ~(size_t)255) + sizeof(BatchTile) * nt + 256;
+    return HEOM_OK;
+}
+
+int heom_batch_commit(heom_batch *b, void *dev, size_t bytes, void *stream) {
+    if (!b || !dev) return fail(HEOM_E_INVAL, "NULL argument");
+    if (reinterpret_cast<uintptr_t>(dev) % 256) return fail(HEOM_E_INVAL, "batch buffer must be 256-byte aligned");
+    size_t need = 0;
+    heom_batch_device_bytes(b, &need);
+    if (bytes < need) return fail(HEOM_E_TOO_LARGE, "batch buffer smaller than heom_batch_device_bytes");
+    const size_t ns = b->slots.size();
+    const size_t tile_off = (sizeof(SlotRec) * ns + 255) & ~(size_t)255;
+    std::vector<unsigned char> img(need, 0);
+    SlotRec *recs = reinterpret_cast<SlotRec *>(img.data());
+    BatchTile *tl = reinterpret_cast<BatchTile *>(img.data() + tile_off);
+    b->groups.clear();
+    b->block = 64;
+    b->lds = 0;
+    size_t k = 0;
+    for (int m = 1; m <= HEOM_MAX_M; ++m) {
+        const size_t first = k;
+        for (size_t i = 0; i < ns; ++i) {
+            const BatchSlotHost &S = b->slots[i];
+            if (!S.used || S.tables->t.m != m) continue;
+            const HostTables &t = S.tables->t;
+            const size_t n = t.n_var;
+            SlotRec &R = recs[i];
+            R.img = static_cast<const unsigned char *>(t.dev);
+            R.params = static_cast<const unsigned char *>(S.params);
+            unsigned char *wb = static_cast<unsigned char *>(S.work);
+            R.y = static_cast<double2 *>(S.y);
+            R.w0 = reinterpret_cast<double2 *>(wb);
+            R.w1 = R.w0 + n;
+            R.u1 = reinterpret_cast<float2 *>(wb + 16 * n);
+            R.u2 = R.u1 + n;
+            R.obs = S.obs;
+            R.obs_every = S.obs_every;
+            R.obs_cap = S.obs_cap;
+            R.step0 = S.steps;
+            R.dt = S.dt;
+            for (uint32_t j = 0; j < t.tiles.size(); ++j) tl[k++] = BatchTile{(uint32_t)i, j};
+            b->block = std::max<uint32_t>(b->block, (uint32_t)t.tile_vars);
+            b->lds = std::max<uint32_t>(b->lds, t.lds_bytes);
+        }
+        if (k > first) b->groups.push_back({m, {(uint32_t)first, (uint32_t)(k - first)}});
+    }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    HIP_TRY(hipMemcpyAsync(dev, img.data(), need, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    b->dev = dev;
+    b->dev_bytes = bytes;
+    b->committed = true;
+    b->steps_since_commit = 0;
+    return HEOM_OK;
+}
+
+int heom_batch_propagate(heom_batch *b, int64_t nsteps, int precision, void *stream) {
+    if (!b) return fail(HEOM_E_INVAL, "batch is NULL");
+    if (!b->committed) return fail(HEOM_E_STATE, "batch changed since the last heom_batch_commit");
+    if (nsteps < 0) return fail(HEOM_E_INVAL, "nsteps < 0");
+    if (precision != HEOM_FP64 && precision != HEOM_FP32) return fail(HEOM_E_INVAL, "unknown precision");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const uint32_t policy = 6u;
+    for (int64_t st = 1; st <= nsteps; ++st)
+        for (int stage = 0; stage < 4; ++stage) {
+            int rc = precision == HEOM_FP64 ? batch_launch<HEOM_FP64>(b, s, stage, st, policy)
+                                            : batch_launch<HEOM_FP32>(b, s, stage, st, policy);
+            if (rc) return rc;
+        }
+    if (precision == HEOM_FP32 && (nsteps & 1)) {
+        for (const auto &S : b->slots) {
+            if (!S.used) continue;
+            hipLaunchKernelGGL(copy_kernel, dim3(256), dim3(256), 0, s, static_cast<const double2 *>(S.work),
+                               static_cast<double2 *>(S.y), S.tables->t.n_var);
+            HIP_TRY(hipGetLastError());
+        }
+    }
+    b->steps_since_commit += nsteps;
+    for (auto &S : b->slots)
+        if (S.used) S.steps += nsteps;
+    return HEOM_OK;
+}
+
+int heom_batch_slot_steps(const heom_batch *b, int32_t slot, int64_t *steps) {
+    if (!b || !steps || slot < 0 || (size_t)slot >= b->slots.size()) return fail(HEOM_E_INVAL, "bad argument");
+    *steps = b->slots[(size_t)slot].steps;
+    return HEOM_OK;
+}
+
+void heom_batch_free(heom_batch *b) { delete b; }
 
 const char *heom_last_error(void) { return g_err.c_str(); }
 

@@ -155,6 +155,10 @@ int set_params(HostTables *t, const heom_problem *p, std::string *err);
 int make_tiles(HostTables *t, int tile_vars, std::string *err);
 void expand_gathers(const HostTables &t, uint32_t p, std::vector<uint32_t> *out);
 void pack_image(HostTables *t);
+size_t image_bytes(const HostTables &t);
+// [InstParams + coefficient tables] of problem p on the structure of t, laid
+// out as the head of t's device image (bytes [0, off_hdr)).
+int pack_params(const HostTables &t, const heom_problem *p, std::vector<unsigned char> *out, std::string *err);
 size_t tier0_size(const HostTables &t);
 
 inline uint32_t vcomp(uint64_t v, int k) { return (uint32_t)((v >> (8 * k)) & 0xffu); }

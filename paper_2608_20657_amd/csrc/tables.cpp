@@ -536,43 +536,78 @@ int set_params(HostTables *t, const heom_problem *p, std::string *err) {
 
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-void pack_image(HostTables *t) {
+// Scalars, bath coefficients and section offsets of the device image.
+// `num` supplies the numeric parameters, `st` the structure.
+static InstParams make_params(const HostTables &num, const HostTables &st) {
     InstParams ip{};
-    const heom_problem &p = t->prob;
+    const heom_problem &p = num.prob;
     ip.g = p.g;
     ip.delta = p.eps - p.omega_c;
     ip.kappa = p.kappa;
     ip.term = p.terminator;
-    ip.npool = (double)(t->N - t->d);
-    ip.Nd = (double)t->N;
-    ip.inv_sqrtN = 1.0 / std::sqrt((double)t->N);
-    double th = 0.5 * std::atan2(2.0 * p.g * std::sqrt((double)t->N), p.omega_c - p.eps);
+    ip.npool = (double)(num.N - st.d);
+    ip.Nd = (double)num.N;
+    ip.inv_sqrtN = 1.0 / std::sqrt((double)num.N);
+    double th = 0.5 * std::atan2(2.0 * p.g * std::sqrt((double)num.N), p.omega_c - p.eps);
     ip.cos_th = std::cos(th);
     ip.sin_th = std::sin(th);
-    for (int k = 0; k < t->m; ++k) {
-        ip.nu[k] = t->nu[k];
-        ip.cr[k] = t->c[2 * k];
-        ip.ci[k] = t->c[2 * k + 1];
-        ip.ccr[k] = t->cc[2 * k];
-        ip.cci[k] = t->cc[2 * k + 1];
+    for (int k = 0; k < st.m; ++k) {
+        ip.nu[k] = num.nu[k];
+        ip.cr[k] = num.c[2 * k];
+        ip.ci[k] = num.c[2 * k + 1];
+        ip.ccr[k] = num.cc[2 * k];
+        ip.cci[k] = num.cc[2 * k + 1];
     }
-    ip.m = t->m;
-    ip.L = t->L;
-    ip.d = t->d;
-    ip.n_pat = (int32_t)t->hdr.size();
-    ip.n_var = t->n_var;
-    ip.n_tiles = (uint32_t)t->tiles.size();
-    ip.tile_vars = (uint32_t)t->tile_vars;
-    ip.max_np = t->max_np;
-    ip.max_nc = t->max_nc;
-    ip.max_ng = t->max_ng;
-    ip.lds_bytes = t->lds_bytes;
+    ip.m = st.m;
+    ip.L = st.L;
+    ip.d = st.d;
+    ip.n_pat = (int32_t)st.hdr.size();
+    ip.n_var = st.n_var;
+    ip.n_tiles = (uint32_t)st.tiles.size();
+    ip.tile_vars = (uint32_t)st.tile_vars;
+    ip.max_np = st.max_np;
+    ip.max_nc = st.max_nc;
+    ip.max_ng = st.max_ng;
+    ip.lds_bytes = st.lds_bytes;
     size_t o = align256(sizeof(InstParams));
-    ip.off_lut = o;   o = align256(o + t->lut.size() * sizeof(double));
-    ip.off_hdr = o;   o = align256(o + t->hdr.size() * sizeof(PatHdr));
-    ip.off_cat = o;   o = align256(o + t->cat.size() * sizeof(CatRec));
-    ip.off_gidx = o;  o = align256(o + t->gidx.size() * sizeof(uint32_t));
-    ip.off_tile = o;  o = align256(o + t->tiles.size() * sizeof(TileRec));
+    ip.off_lut = o;   o = align256(o + st.lut.size() * sizeof(double));
+    ip.off_hdr = o;   o = align256(o + st.hdr.size() * sizeof(PatHdr));
+    ip.off_cat = o;   o = align256(o + st.cat.size() * sizeof(CatRec));
+    ip.off_gidx = o;  o = align256(o + st.gidx.size() * sizeof(uint32_t));
+    ip.off_tile = o;
+    return ip;
+}
+
+size_t image_bytes(const HostTables &t) {
+    const InstParams ip = make_params(t, t);
+    return align256(ip.off_tile + t.tiles.size() * sizeof(TileRec));
+}
+
+int pack_params(const HostTables &t, const heom_problem *p, std::vector<unsigned char> *out, std::string *err) {
+    int rc = check_params(p, err);
+    if (rc) return rc;
+    auto key = [](int64_t N, int m, int L, int d) {
+        return std::vector<int64_t>{std::min<int64_t>(N, (int64_t)L + d + 2), m, L, d};
+    };
+    if (key(p->N, p->m, p->L, p->d) != key(t.N, t.m, t.L, t.d)) {
+        *err = "structure key (min(N, L+d+2), m, L, d) differs from the tables";
+        return HEOM_E_INVAL;
+    }
+    HostTables num;
+    num.m = t.m;
+    num.L = t.L;
+    num.d = t.d;
+    copy_numeric(&num, p);
+    const InstParams ip = make_params(num, t);
+    out->assign(ip.off_hdr, 0);
+    std::memcpy(out->data(), &ip, sizeof ip);
+    std::memcpy(out->data() + ip.off_lut, num.lut.data(), num.lut.size() * sizeof(double));
+    return HEOM_OK;
+}
+
+void pack_image(HostTables *t) {
+    const InstParams ip = make_params(*t, *t);
+    const size_t o = image_bytes(*t);
     t->image.assign(o, 0);
     std::memcpy(t->image.data(), &ip, sizeof ip);
     std::memcpy(t->image.data() + ip.off_lut, t->lut.data(), t->lut.size() * sizeof(double));

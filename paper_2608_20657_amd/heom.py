@@ -28,7 +28,10 @@ ERRORS = {-1: "E_INVAL", -2: "E_NOMEM", -3: "E_TOO_LARGE", -4: "E_HIP", -5: "E_N
 SYMBOLS = ["heom_build_tables", "heom_set_params", "heom_table_info", "heom_upload", "heom_tier0_pure",
            "heom_init_state", "heom_rhs", "heom_propagate", "heom_observables", "heom_export_layout",
            "heom_export_coefficients", "heom_free_tables", "heom_last_error", "heom_version",
-           "heom_set_tuning", "heom_get_tuning", "heom_work_status"]
+           "heom_set_tuning", "heom_get_tuning", "heom_work_status", "heom_params_bytes",
+           "heom_upload_params", "heom_batch_create", "heom_batch_set_slot", "heom_batch_clear_slot",
+           "heom_batch_device_bytes", "heom_batch_commit", "heom_batch_propagate", "heom_batch_slot_steps",
+           "heom_batch_free"]
 
 
 class HeomError(RuntimeError):
@@ -61,6 +64,10 @@ class _Sizes(ctypes.Structure):
 
 
 def _load():
+    # PyTorch ships its own HIP runtime and loads it by file name. Loading it
+    # first makes libheom bind to that same runtime (same soname); loading
+    # libheom first would put two HIP/HSA runtimes into the process.
+    import torch  # noqa: F401
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
                           "or python paper_2608_20657_amd/build.py")
@@ -81,6 +88,16 @@ def _load():
         "heom_set_tuning": [vp, ctypes.POINTER(_Tuning)],
         "heom_get_tuning": [vp, ctypes.POINTER(_Tuning)],
         "heom_work_status": [vp, vp, ctypes.c_size_t, vp],
+        "heom_params_bytes": [vp, ctypes.POINTER(ctypes.c_size_t)],
+        "heom_upload_params": [vp, ctypes.POINTER(_Problem), vp, ctypes.c_size_t, vp],
+        "heom_batch_create": [ctypes.c_int32, ctypes.POINTER(vp)],
+        "heom_batch_set_slot": [vp, ctypes.c_int32, vp, vp, vp, vp, ctypes.c_size_t, ctypes.c_double, vp,
+                                i64, i64],
+        "heom_batch_clear_slot": [vp, ctypes.c_int32],
+        "heom_batch_device_bytes": [vp, ctypes.POINTER(ctypes.c_size_t)],
+        "heom_batch_commit": [vp, vp, ctypes.c_size_t, vp],
+        "heom_batch_propagate": [vp, i64, ctypes.c_int, vp],
+        "heom_batch_slot_steps": [vp, ctypes.c_int32, ctypes.POINTER(i64)],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -88,6 +105,8 @@ def _load():
         f.restype = ctypes.c_int
     lib.heom_free_tables.argtypes = [vp]
     lib.heom_free_tables.restype = None
+    lib.heom_batch_free.argtypes = [vp]
+    lib.heom_batch_free.restype = None
     lib.heom_last_error.restype = ctypes.c_char_p
     lib.heom_version.restype = ctypes.c_char_p
     return lib
@@ -249,6 +268,69 @@ class Tables:
         _check(LIB.heom_export_coefficients(self._h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                                             need.value, ctypes.byref(need)))
         return out
+
+
+    def params_bytes(self) -> int:
+        n = ctypes.c_size_t()
+        _check(LIB.heom_params_bytes(self._h, ctypes.byref(n)))
+        return n.value
+
+    def upload_params(self, problem, device_buffer, stream=None):
+        """Write the parameter block of `problem` (same structure key) into a
+        caller-owned uint8 device buffer."""
+        s, keep = _problem_struct(problem)
+        nbytes = device_buffer.numel() * device_buffer.element_size()
+        _check(LIB.heom_upload_params(self._h, ctypes.byref(s), _ptr(device_buffer), nbytes, _stream(stream)))
+
+
+class Batch:
+    """A set of slots, each an independent problem propagated together."""
+
+    def __init__(self, capacity: int):
+        h = ctypes.c_void_p()
+        _check(LIB.heom_batch_create(int(capacity), ctypes.byref(h)))
+        self._h = h
+        self.capacity = capacity
+        self._keep = {}      # slot -> objects that must outlive the slot
+        self.image = None
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and LIB is not None:
+            LIB.heom_batch_free(h)
+            self._h = None
+
+    def set_slot(self, slot: int, tables: Tables, y, work, dt: float, params=None, obs=None,
+                 obs_every: int = 0):
+        cap = 0 if obs is None else obs.numel() // HEOM_NOBS
+        wbytes = work.numel() * work.element_size()
+        _check(LIB.heom_batch_set_slot(self._h, int(slot), tables.handle,
+                                       _ptr(params) if params is not None else None, _ptr(y), _ptr(work), wbytes,
+                                       float(dt), _ptr(obs) if obs is not None else None, int(obs_every), int(cap)))
+        self._keep[slot] = (tables, params, y, work, obs)
+
+    def clear_slot(self, slot: int):
+        _check(LIB.heom_batch_clear_slot(self._h, int(slot)))
+        self._keep.pop(slot, None)
+
+    def device_bytes(self) -> int:
+        n = ctypes.c_size_t()
+        _check(LIB.heom_batch_device_bytes(self._h, ctypes.byref(n)))
+        return n.value
+
+    def commit(self, torch, stream=None):
+        """Upload slot records and the tile list into a fresh device buffer."""
+        buf = torch.empty(max(self.device_bytes(), 256), dtype=torch.uint8, device="cuda")
+        _check(LIB.heom_batch_commit(self._h, _ptr(buf), buf.numel(), _stream(stream)))
+        self.image = buf
+
+    def propagate(self, nsteps: int, precision: int = HEOM_FP64, stream=None):
+        _check(LIB.heom_batch_propagate(self._h, int(nsteps), int(precision), _stream(stream)))
+
+    def slot_steps(self, slot: int) -> int:
+        n = ctypes.c_int64()
+        _check(LIB.heom_batch_slot_steps(self._h, int(slot), ctypes.byref(n)))
+        return n.value
 
 
 def version() -> str:
