@@ -252,10 +252,11 @@ int heom_batch_create(int32_t capacity, heom_batch **out);
  * complex128, initialized e.g. by heom_init_state), a work buffer of at least
  * work_bytes_fp64 bytes, its time step, and optionally an observable buffer
  * of obs_capacity samples of HEOM_NOBS doubles: sample j holds the
- * observables after j*obs_every steps of this slot (sample 0, the initial
- * state, is the caller's, e.g. heom_observables). All pointers are caller
- * device memory. The slot's step count restarts at 0. Takes effect at the
- * next heom_batch_commit. */
+ * observables after j*obs_every steps of this slot; sample 0, the initial
+ * state evaluated with the slot's own parameters, is written by the next
+ * heom_batch_commit, so y_dev must be initialized before it. All pointers
+ * are caller device memory. The slot's step count restarts at 0. Takes
+ * effect at the next heom_batch_commit. */
 int heom_batch_set_slot(heom_batch *b, int32_t slot, const heom_tables *t, const void *params_dev, void *y_dev,
                         void *work_dev, size_t work_bytes, double dt, double *obs_dev, int64_t obs_every,
                         int64_t obs_capacity);
@@ -267,8 +268,9 @@ int heom_batch_clear_slot(heom_batch *b, int32_t slot);
 int heom_batch_device_bytes(const heom_batch *b, size_t *bytes);
 
 /* Upload the slot records and the tile list (grouped by m) into caller
- * device memory (256-byte aligned, >= heom_batch_device_bytes),
- * synchronously on `stream`. Required after any set/clear. */
+ * device memory (256-byte aligned, >= heom_batch_device_bytes), and write
+ * observable sample 0 of every slot that has not stepped yet, synchronously
+ * on `stream`. Required after any set/clear. */
 int heom_batch_commit(heom_batch *b, void *dev, size_t bytes, void *stream);
 
 /* Advance every occupied slot by nsteps RK4 steps of its own dt (the same

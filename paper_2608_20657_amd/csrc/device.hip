@@ -1258,6 +1258,15 @@ int heom_batch_commit(heom_batch *b, void *dev, size_t bytes, void *stream) {
     }
     hipStream_t s = static_cast<hipStream_t>(stream);
     HIP_TRY(hipMemcpyAsync(dev, img.data(), need, hipMemcpyHostToDevice, s));
+    // Row 0 of a new slot's observables: the initial state, evaluated with
+    // the slot's own parameter block (as heom_propagate does at its start).
+    for (const auto &S : b->slots) {
+        if (!S.used || S.steps != 0 || !S.obs || S.obs_every <= 0 || S.obs_cap <= 0) continue;
+        Dev D = dev_view(S.tables->t);
+        D.ip = static_cast<const InstParams *>(S.params);
+        hipLaunchKernelGGL(observables_kernel, dim3(1), dim3(64), 0, s, D, static_cast<const double2 *>(S.y), S.obs);
+        HIP_TRY(hipGetLastError());
+    }
     HIP_TRY(hipStreamSynchronize(s));
     b->dev = dev;
     b->dev_bytes = bytes;

@@ -166,7 +166,7 @@ class Tables:
 
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h is not None and h.value:
+        if h is not None and h.value and LIB is not None:
             LIB.heom_free_tables(h)
             self._h = None
 
