@@ -35,6 +35,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -125,6 +127,135 @@ def cpu_baseline(p, tier0_amp, dt, budget_s):
                 seconds=round(el, 2), steps=steps)
 
 
+def _rate(ms, n_inst, vars_total, steps):
+    sec = ms / 1e3
+    return {"ms_per_step": round(ms / steps, 4), "instance_steps_per_s": n_inst * steps / sec,
+            "rhs_updates_per_s": vars_total * 4 * steps / sec}
+
+
+def batched_section(torch, steps, n=512, seed=0, dt=0.02):
+    """Many independent problems at once: the batched launch (every instance
+    in one launch per stage and per m) in FP64 and FP32-bulk, against the
+    plain per-instance FP64 propagator called once per instance. Time per
+    mode = HIP events around `steps` RK4 steps of all instances (each
+    instance's tables and state already resident)."""
+    from paper_2608_20657_amd import heom, serve as S, workloads as W
+    ps = W.draw_batch(n, seed)
+    t0 = time.perf_counter()
+    structs = {}
+    for q in ps:
+        k = S.structure_key(q)
+        if k not in structs:
+            structs[k] = heom.Tables(q)
+    build_s = time.perf_counter() - t0
+    st = torch.cuda.current_stream()
+    imgs = {}
+    for k, T in structs.items():
+        imgs[k] = torch.empty(S._round(T.info()["table_bytes"]), dtype=torch.uint8, device="cuda")
+        T.upload(imgs[k], st)
+    inst = []
+    for q in ps:
+        T = structs[S.structure_key(q)]
+        info = T.info()
+        params = torch.empty(S._round(T.params_bytes()), dtype=torch.uint8, device="cuda")
+        T.upload_params(q, params, st)
+        y = torch.empty(info["n_var"], dtype=torch.complex128, device="cuda")
+        work = torch.empty(S._round(info["work_bytes_fp64"]), dtype=torch.uint8, device="cuda")
+        inst.append((q, T, params, y, work, T.tier0_pure(1.0, 0.0, [0.0] * q.d), info["n_var"]))
+    nv = sum(x[6] for x in inst)
+    batch = heom.Batch(len(inst))
+    for i, (q, T, params, y, work, t0v, _) in enumerate(inst):
+        batch.set_slot(i, T, y, work, dt, params=params)
+    batch.commit(torch, st)
+    out = {"workload": f"{n} independent problems drawn with seed {seed}: N~U{{4..5000}}, m~U{{1..4}}, "
+                       "L~U{3..10}, g~U[0.002,0.03], lam~U[0.005,0.05], gam~U[0.02,0.2], kappa~U[0,0.02], "
+                       "kT=0.025, resonant, d=0, rho(0)=|c><c|, dt=0.02",
+           "instances": len(inst), "unique_vars_total": nv, "structure_keys": len(structs),
+           "largest_instance_vars": max(x[6] for x in inst),
+           "median_instance_vars": int(sorted(x[6] for x in inst)[len(inst) // 2]),
+           "steps": steps, "table_build_s": round(build_s, 2)}
+    for prec, name in ((0, "fp64_batched"), (1, "fp32_batched")):
+        for q, T, params, y, work, t0v, _ in inst:
+            T.init_state(t0v, y, st)
+        batch.propagate(1, prec, st)                       # warm-up step
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        batch.propagate(steps, prec, st)
+        e1.record(st)
+        torch.cuda.synchronize()
+        out[name] = _rate(e0.elapsed_time(e1), len(inst), nv, steps)
+        out[name]["finite"] = bool(all(torch.isfinite(x[3][:64]).all().item() for x in inst[:64]))
+    del batch
+    total_ms = 0.0
+    for q, T, params, y, work, t0v, _ in inst:            # plain: one problem at a time
+        T.set_params(q)
+        T.upload(imgs[S.structure_key(q)], st)
+        T.init_state(t0v, y, st)
+        T.propagate(y, work, dt, 1, 0, None, 0, st)        # warm-up step
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        T.propagate(y, work, dt, steps, 0, None, 0, st)
+        e1.record(st)
+        torch.cuda.synchronize()
+        total_ms += e0.elapsed_time(e1)
+    out["fp64_plain_one_at_a_time"] = _rate(total_ms, len(inst), nv, steps)
+    base = out["fp64_plain_one_at_a_time"]["instance_steps_per_s"]
+    out["speedup_fp64_batched_vs_plain"] = round(out["fp64_batched"]["instance_steps_per_s"] / base, 3)
+    out["speedup_fp32_batched_vs_plain"] = round(out["fp32_batched"]["instance_steps_per_s"] / base, 3)
+    del inst, imgs
+    torch.cuda.empty_cache()
+    return out
+
+
+POP_COLS = [1, 2, 4, 5, 6]
+
+
+def serving_point(torch, rate, window, deadline, seed=1, precision=1, budget_gib=256.0,
+                  lanes=(1 << 20,), capacity=(256, 32), fifo=True):
+    """Poisson arrivals of propagation requests (problems drawn as in the
+    batched workload, plus a horizon of U{1000..20000} steps, obs every 100
+    steps, dt=0.02). Arrivals in [0, window) are submitted; the run ends at
+    `deadline` seconds or when all are done. The continuous-batching server
+    (precision as given) and the plain FP64 propagator one request at a time
+    (FIFO) replay the same trace."""
+    from paper_2608_20657_amd import serve as S, workloads as W
+    arr = W.arrival_times(rate, window, seed)
+    ps = W.draw_batch(len(arr), seed=seed, with_horizon=True)
+    reqs = S.make_requests(ps, arr, dt=0.02, obs_every=100)
+    out = {"workload": f"Poisson arrivals at {rate} req/s for {window} s (seed {seed}); problems as the batched "
+                       "workload plus horizon U{1000..20000} steps, dt=0.02, observables every 100 steps",
+           "rate_req_per_s": rate, "window_s": window, "deadline_s": deadline, "requests": len(reqs),
+           "offered_rhs_updates_per_s": None}
+    srv = S.Server(torch, int(budget_gib * (1 << 30)), lanes=list(lanes), capacity=list(capacity),
+                   precision=precision)
+    srv.prepare(ps)
+    work = sum(srv.structs[S.structure_key(q)].n_var * 4 * r.horizon for q, r in zip(ps, reqs))
+    out["offered_rhs_updates_per_s"] = work / window
+    st = srv.run(reqs, window, deadline)
+    st["precision"] = "fp32-bulk" if precision == 1 else "fp64"
+    st["budget_gib"] = budget_gib
+    st["lanes_vars_threshold"] = list(lanes)
+    out["served"] = st
+    if fifo:
+        ff = S.Fifo(torch, precision=0)
+        ff.prepare(ps)
+        st2 = ff.run(reqs, window, deadline)
+        st2["precision"] = "fp64"
+        out["plain_fifo"] = st2
+        got = {r.rid: r.obs for r in srv.results}
+        errs = [float(np.abs(got[r.rid][:, POP_COLS] - r.obs[:, POP_COLS]).max()) for r in ff.results if r.rid in got]
+        out["max_abs_population_diff_served_vs_plain_fp64"] = max(errs) if errs else None
+        out["compared_requests"] = len(errs)
+        if st2["solves_per_s"] > 0:
+            out["solves_per_s_ratio_served_over_plain"] = round(st["solves_per_s"] / st2["solves_per_s"], 3)
+        del ff
+    del srv
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -139,6 +270,14 @@ def main():
     ap.add_argument("--roofline-only", action="store_true",
                     help="skip the localized solve (for profiling the roofline kernel alone)")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--batched-steps", type=int, default=5)
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--serve-rate", type=float, default=1.0)
+    ap.add_argument("--serve-window", type=float, default=15.0)
+    ap.add_argument("--serve-deadline", type=float, default=30.0)
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-sweep", type=str, default="",
+                    help="comma-separated arrival rates: print one serving JSON line per rate and exit")
     ap.add_argument("--calibrate-copy-mb", type=int, default=0,
                     help="also run a plain device-to-device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -155,6 +294,11 @@ def main():
     from paper_2608_20657_amd import heom, workloads as W
 
     precision = 0 if args.precision == "fp64" else 1
+    if args.serve_sweep:
+        for r in [float(x) for x in args.serve_sweep.split(",") if x]:
+            rec = serving_point(torch, r, args.serve_window, args.serve_deadline)
+            print(json.dumps({"serving_sweep_point": rec}), flush=True)
+        return
     if args.calibrate_copy_mb:
         nb = args.calibrate_copy_mb << 20
         src = torch.ones(nb // 8, dtype=torch.float64, device="cuda")
@@ -252,6 +396,13 @@ def main():
             "table_build_s": round(build_s, 2),
         }
         del ry, img2, TR
+
+    if args.roofline_only:
+        args.no_batched = args.no_serve = True
+    if not args.no_batched:
+        out["batched"] = batched_section(torch, args.batched_steps)
+    if not args.no_serve:
+        out["serving"] = serving_point(torch, args.serve_rate, args.serve_window, args.serve_deadline)
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(p, lambda i: 1.0 if i == 1 else 0.0, dt, args.cpu_seconds)

@@ -40,8 +40,14 @@ struct heom_batch {
     void *dev = nullptr;
     size_t dev_bytes = 0;
     int64_t steps_since_commit = 0;
-    uint32_t block = 64, lds = 0;
-    std::vector<std::pair<int, std::pair<uint32_t, uint32_t>>> groups;  // (m, (first tile, count))
+    // One launch per group: tiles of one m, one tile size and one tier class
+    // (top-tier tiles have no up moves and run a lighter kernel variant).
+    struct Group {
+        int m;
+        bool top;
+        uint32_t block, lds, first, count;
+    };
+    std::vector<Group> groups;
 };
 
 namespace {
@@ -189,16 +195,6 @@ __device__ __forceinline__ void st_stream(float2 *p, double2 v) {
     __builtin_nontemporal_store(w, reinterpret_cast<fvec2 *>(p));
 }
 
-// Copy n records of T (a multiple of 8 bytes) from global to LDS, coalesced.
-template <class T>
-__device__ __forceinline__ void stage_copy(T *dst, const T *src, uint32_t n) {
-    static_assert(sizeof(T) % 8 == 0, "record size");
-    const uint2 *s = reinterpret_cast<const uint2 *>(src);
-    uint2 *d = reinterpret_cast<uint2 *>(dst);
-    const uint32_t words = n * (uint32_t)(sizeof(T) / 8);
-    for (uint32_t i = threadIdx.x; i < words; i += blockDim.x) d[i] = s[i];
-}
-
 // Vectors one stage reads and writes:
 //   out[i] = base(i) + alpha * ((M_u in)[i] + extra_scale * extra[i])
 // with in = in64 (+ in32), base = in (BASE 1) or ybase (BASE 2) or 0.
@@ -238,11 +234,36 @@ __device__ __forceinline__ Smem carve(unsigned char *smem, const InstParams &P) 
     return S;
 }
 
-__device__ __forceinline__ void stage_meta(const Dev &D, const TileRec &TR, const Smem &S) {
-    stage_copy(S.hdr, D.hdr + TR.p0, TR.np);
-    stage_copy(S.cat, D.cat + TR.c0, TR.nc);
-    const uint32_t *g = D.gidx + TR.g0;
-    for (uint32_t i = threadIdx.x; i < TR.ng; i += blockDim.x) S.gix[i] = g[i];
+// Copy a tile's metadata (pattern headers, categories, gather indices) and,
+// if lut_words > 0, the coefficient tables into LDS, as 16-byte words. The
+// four sources are one index range, and each thread issues its loads (two
+// words per round) before it writes any of them, so the copy costs about
+// one memory latency instead of one per array and round. Every section
+// starts 16-byte aligned in the image and in LDS (a tile's gather list is
+// padded to a multiple of four indices).
+__device__ __forceinline__ void stage_tile(const Dev &D, const TileRec &TR, const Smem &S, uint32_t lut_words) {
+    const uint32_t e1 = 2u * TR.np, e2 = e1 + TR.nc, e3 = e2 + ((TR.ng + 3u) >> 2), e4 = e3 + lut_words;
+    const uint4 *sh = reinterpret_cast<const uint4 *>(D.hdr + TR.p0);
+    const uint4 *sc = reinterpret_cast<const uint4 *>(D.cat + TR.c0);
+    const uint4 *sg = reinterpret_cast<const uint4 *>(D.gidx + TR.g0);
+    const uint4 *sl = reinterpret_cast<const uint4 *>(D.lut);
+    uint4 *dh = reinterpret_cast<uint4 *>(S.hdr), *dc = reinterpret_cast<uint4 *>(S.cat);
+    uint4 *dg = reinterpret_cast<uint4 *>(S.gix), *dl = reinterpret_cast<uint4 *>(S.lut);
+    const uint32_t bd = blockDim.x;
+    for (uint32_t b = threadIdx.x; b < e4; b += 2u * bd) {
+        uint4 r0 = make_uint4(0u, 0u, 0u, 0u), r1 = r0;
+        const uint32_t i0 = b, i1 = b + bd;
+        auto src = [&](uint32_t i) {
+            return i < e1 ? sh + i : (i < e2 ? sc + (i - e1) : (i < e3 ? sg + (i - e2) : sl + (i - e3)));
+        };
+        auto dst = [&](uint32_t i) {
+            return i < e1 ? dh + i : (i < e2 ? dc + (i - e1) : (i < e3 ? dg + (i - e2) : dl + (i - e3)));
+        };
+        if (i0 < e4) r0 = *src(i0);
+        if (i1 < e4) r1 = *src(i1);
+        if (i0 < e4) *dst(i0) = r0;
+        if (i1 < e4) *dst(i1) = r1;
+    }
 }
 
 // Exclusive prefix sum of x over the threads of the workgroup (thread order).
@@ -263,8 +284,11 @@ __device__ __forceinline__ uint32_t wg_exclusive_scan(uint32_t x) {
     return base + v - x;
 }
 
+// 16-byte words of the coefficient tables (2 m (L+1) doubles).
+__device__ __forceinline__ uint32_t lut_words(const InstParams &P) { return (uint32_t)P.m * (uint32_t)(P.L + 1); }
+
 __device__ __forceinline__ void stage_lut(const Dev &D, const InstParams &P, double *lut) {
-    const uint32_t n = 2u * (uint32_t)P.m * (uint32_t)(P.L + 1);
+    const uint32_t n = 2u * lut_words(P);
     for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) lut[i] = D.lut[i];
 }
 
@@ -280,8 +304,9 @@ __device__ __forceinline__ double2 load_in(const StageArgs &a, uint32_t j) {
     return v;
 }
 
-// One fused stage over one tile. The tile's metadata must already be in LDS
-// (stage_meta) and the coefficient tables too (stage_lut).
+// One fused stage over one tile. The tile's metadata and the coefficient
+// tables are staged into LDS first (stage_tile), unless `stage` is NULL and
+// they are there already.
 //
 // Every variable has up to 4M hierarchy gathers ("slots"): for each channel
 // k, the row molecule raised (k), lowered (M+k), the column molecule raised
@@ -304,9 +329,22 @@ __device__ __forceinline__ double2 load_own(const StageArgs &a, uint32_t j) {
 
 template <int M, bool HAS64, bool HAS32, int BASE, bool EXTRA, bool OUT64, bool TOP>
 __device__ __forceinline__ void process_tile(const InstParams &P, const TileRec &TR, const Smem &S,
-                                             const StageArgs &a, bool first_tile) {
+                                             const StageArgs &a, bool first_tile, const Dev *stage,
+                                             uint32_t lut_w) {
     const uint32_t t = threadIdx.x;
     const bool active = t < TR.nv;
+    // The loads that depend on the thread alone go out first and stay in
+    // flight while the tile's metadata is staged (the barriers below wait
+    // for LDS traffic only).
+    double2 own = make_double2(0.0, 0.0), ybv = make_double2(0.0, 0.0);
+    float2 ex = make_float2(0.0f, 0.0f);
+    if (active) {
+        own = load_own<HAS64, HAS32>(a, TR.v0 + t);
+        if (BASE == BASE_Y) ybv = (a.policy & 2u) ? ld_stream(a.ybase + TR.v0 + t) : a.ybase[TR.v0 + t];
+        if (EXTRA) ex = a.extra[TR.v0 + t];
+    }
+    if (stage != nullptr) stage_tile(*stage, TR, S, lut_w);
+    __syncthreads();
     int kind = KIND_Z, A = 0, B = 0, q = 0, r = 0;
     uint32_t base = 0, lo = 0;
     PatHdr H{};
@@ -315,8 +353,7 @@ __device__ __forceinline__ void process_tile(const InstParams &P, const TileRec 
     uint32_t idx[4 * M];
     uint32_t live = 0;
     double2 v[4 * M];
-    double2 own = make_double2(0.0, 0.0), ybv = make_double2(0.0, 0.0);
-    float2 ex = make_float2(0.0f, 0.0f);
+    double2 hier = make_double2(0.0, 0.0);
     if (active) {
         uint32_t hi = TR.np;  // block lo holds variable t
         while (hi - lo > 1) {
@@ -354,25 +391,35 @@ __device__ __forceinline__ void process_tile(const InstParams &P, const TileRec 
             const bool up_slot = ((j / M) & 1) == 0;   // slots 0..M-1 and 2M..3M-1 are up moves
             idx[j] = (!(TOP && up_slot) && ((live >> j) & 1u)) ? S.gix[goff + __popc(live & ((1u << j) - 1u))] : 0u;
         }
-        own = load_own<HAS64, HAS32>(a, TR.v0 + t);
-        // the base vector and the extra term only depend on t: issue them now
-        if (BASE == BASE_Y) ybv = (a.policy & 2u) ? ld_stream(a.ybase + TR.v0 + t) : a.ybase[TR.v0 + t];
-        if (EXTRA) ex = a.extra[TR.v0 + t];
 #pragma unroll
         for (int j = 0; j < 4 * M; ++j) {
             const bool up_slot = ((j / M) & 1) == 0;
             v[j] = (!(TOP && up_slot) && ((live >> j) & 1u)) ? load_in<HAS64, HAS32>(a, idx[j]) : make_double2(0.0, 0.0);
         }
         S.val[t] = own;
+        // hierarchy: row moves -i sqrt((n+1)|c|), -i sqrt(n/|c|) c_k (P: c_k - cc_k);
+        // column moves +i sqrt((n+1)|c|), +i sqrt(n/|c|) cc_k. Summed before the
+        // barrier, so the gathered values are dead during the grouped sums.
+        const int L1 = P.L + 1;
+        const double *up = S.lut;
+        const double *dn = S.lut + M * L1;
+#pragma unroll
+        for (int k = 0; k < M; ++k) {
+            const uint32_t nq = vbyte(cq.vec, k), nr = vbyte(cr2.vec, k);
+            const double dq = dn[k * L1 + nq], dr = dn[k * L1 + nr];
+            const double cre = kind == KIND_P ? P.cr[k] - P.ccr[k] : P.cr[k];
+            const double cim = kind == KIND_P ? P.ci[k] - P.cci[k] : P.ci[k];
+            if (!TOP) cfma(hier, make_double2(0.0, -up[k * L1 + nq]), v[k]);
+            cfma(hier, make_double2(dq * cim, -dq * cre), v[M + k]);
+            if (!TOP) cfma(hier, make_double2(0.0, up[k * L1 + nr]), v[2 * M + k]);
+            cfma(hier, make_double2(-dr * P.cci[k], dr * P.ccr[k]), v[3 * M + k]);
+        }
     }
     __syncthreads();
 
     double2 res = make_double2(0.0, 0.0);
     if (active) {
         const int G = H.G, G1 = G + 1, nm = G1 * G1;
-        const int L1 = P.L + 1;
-        const double *up = S.lut;
-        const double *dn = S.lut + M * L1;
         const CatRec *cats = S.cat + (H.cat_base - TR.c0);
         auto mult = [&](int c) -> double {
             const CatRec cc = cats[c];
@@ -411,20 +458,7 @@ __device__ __forceinline__ void process_tile(const InstParams &P, const TileRec 
             hsum = csub(sv(0, B), sv(A, 0));
             acc = cscale(-(gam + 2.0 * P.term), own);
         }
-        // hierarchy: row moves -i sqrt((n+1)|c|), -i sqrt(n/|c|) c_k (P: c_k - cc_k);
-        // column moves +i sqrt((n+1)|c|), +i sqrt(n/|c|) cc_k
-#pragma unroll
-        for (int k = 0; k < M; ++k) {
-            const uint32_t nq = vbyte(cq.vec, k), nr = vbyte(cr2.vec, k);
-            const double uq = up[k * L1 + nq], dq = dn[k * L1 + nq];
-            const double ur = up[k * L1 + nr], dr = dn[k * L1 + nr];
-            const double cre = kind == KIND_P ? P.cr[k] - P.ccr[k] : P.cr[k];
-            const double cim = kind == KIND_P ? P.ci[k] - P.cci[k] : P.ci[k];
-            cfma(acc, make_double2(0.0, -uq), v[k]);
-            cfma(acc, make_double2(dq * cim, -dq * cre), v[M + k]);
-            cfma(acc, make_double2(0.0, ur), v[2 * M + k]);
-            cfma(acc, make_double2(-dr * P.cci[k], dr * P.ccr[k]), v[3 * M + k]);
-        }
+        acc = cadd(acc, hier);
         acc.x += P.g * hsum.y;
         acc.y -= P.g * hsum.x;
         if (EXTRA) {
@@ -463,10 +497,7 @@ __global__ __launch_bounds__(MAX_TILE) void stage_kernel(Dev D, StageArgs a, int
     const Smem S = carve(smem, P);
     const uint32_t tile = a.tile0 + (xcd ? xcd_tile(blockIdx.x, gridDim.x) : blockIdx.x);
     const TileRec TR = D.tiles[tile];
-    stage_meta(D, TR, S);
-    stage_lut(D, P, S.lut);
-    __syncthreads();
-    process_tile<M, HAS64, HAS32, BASE, EXTRA, OUT64, TOP>(P, TR, S, a, tile == 0);
+    process_tile<M, HAS64, HAS32, BASE, EXTRA, OUT64, TOP>(P, TR, S, a, tile == 0, &D, lut_words(P));
 }
 
 // Grid-wide barrier for the persistent kernel. Workgroup w publishes its
@@ -543,7 +574,7 @@ __global__ __launch_bounds__(MAX_TILE) void persistent_kernel(Dev D, PersistArgs
     TileRec TR0 = {};
     if (single && t_lo + j < t_hi) {
         TR0 = D.tiles[t_lo + j];
-        stage_meta(D, TR0, S);
+        stage_tile(D, TR0, S, 0u);
     }
     __syncthreads();
     const double h = pa.dt;
@@ -574,17 +605,14 @@ __global__ __launch_bounds__(MAX_TILE) void persistent_kernel(Dev D, PersistArgs
             a.policy = pa.policy;
             for (uint32_t tl = t_lo + j; tl < t_hi; tl += wx) {
                 const TileRec TR = single ? TR0 : D.tiles[tl];
-                if (!single) {
-                    stage_meta(D, TR, S);
-                    __syncthreads();
-                }
+                const Dev *sd = single ? nullptr : &D;   // one tile per workgroup: staged once above
                 if (PREC == HEOM_FP64) {
-                    if (s == 0) process_tile<M, true, false, BASE_IN, false, true, false>(P, TR, S, a, tl == 0);
-                    else process_tile<M, true, false, BASE_Y, false, true, false>(P, TR, S, a, tl == 0);
+                    if (s == 0) process_tile<M, true, false, BASE_IN, false, true, false>(P, TR, S, a, tl == 0, sd, 0u);
+                    else process_tile<M, true, false, BASE_Y, false, true, false>(P, TR, S, a, tl == 0, sd, 0u);
                 } else {
-                    if (s == 0) process_tile<M, true, false, BASE_NONE, false, false, false>(P, TR, S, a, false);
-                    else if (s < 3) process_tile<M, false, true, BASE_NONE, true, false, false>(P, TR, S, a, false);
-                    else process_tile<M, true, true, BASE_Y, false, true, false>(P, TR, S, a, tl == 0);
+                    if (s == 0) process_tile<M, true, false, BASE_NONE, false, false, false>(P, TR, S, a, false, sd, 0u);
+                    else if (s < 3) process_tile<M, false, true, BASE_NONE, true, false, false>(P, TR, S, a, false, sd, 0u);
+                    else process_tile<M, true, true, BASE_Y, false, true, false>(P, TR, S, a, tl == 0, sd, 0u);
                 }
             }
             epoch += 1;
@@ -619,15 +647,35 @@ struct BatchTile {
     uint32_t slot, tile;
 };
 
+// A pointer read from memory has no known address space, so accesses
+// through it would be flat instructions (which also hold up every LDS wait)
+// and its uniform loads could not go through the scalar unit. Slot records
+// only ever hold global-memory addresses: say so.
+template <class T>
+__device__ __forceinline__ T *as_global(T *p) {
+    return (T *)(reinterpret_cast<__attribute__((address_space(1))) T *>(reinterpret_cast<uintptr_t>(p)));
+}
+
 // One RK4 stage of every tile of every slot in a tile list (all of one m).
 // Each variable is computed by the same arithmetic as in stage_kernel, so a
 // problem's trajectory does not depend on the other problems in the batch.
-template <int M, int PREC>
+// SV selects the stage's vector pattern at compile time (FP64: 0 = first
+// stage, 1 = the others; FP32: 0 = first, 1 = second and third, 2 = last),
+// so each instance holds only the registers of its own pattern.
+template <int M, int PREC, bool TOP, int SV>
 __global__ __launch_bounds__(MAX_TILE) void batch_stage_kernel(const SlotRec *slots, const BatchTile *btiles, int s,
                                                              int64_t steps_done, int64_t st, uint32_t policy) {
     extern __shared__ __align__(16) unsigned char smem[];
     const BatchTile B = btiles[blockIdx.x];
-    const SlotRec R = slots[B.slot];
+    SlotRec R = slots[B.slot];
+    R.img = as_global(R.img);
+    R.params = as_global(R.params);
+    R.y = as_global(R.y);
+    R.w0 = as_global(R.w0);
+    R.w1 = as_global(R.w1);
+    R.u1 = as_global(R.u1);
+    R.u2 = as_global(R.u2);
+    R.obs = as_global(R.obs);
     const InstParams &P = *reinterpret_cast<const InstParams *>(R.params);
     Dev D;
     D.ip = &P;
@@ -638,9 +686,7 @@ __global__ __launch_bounds__(MAX_TILE) void batch_stage_kernel(const SlotRec *sl
     D.tiles = reinterpret_cast<const TileRec *>(R.img + P.off_tile);
     const Smem S = carve(smem, P);
     const TileRec TR = D.tiles[B.tile];
-    stage_meta(D, TR, S);
-    stage_lut(D, P, S.lut);
-    __syncthreads();
+    const uint32_t lw = lut_words(P);
     const double h = R.dt;
     const int64_t gst = R.step0 + steps_done + st;   // steps of this slot so far, this one included
     StageArgs a{};
@@ -653,8 +699,8 @@ __global__ __launch_bounds__(MAX_TILE) void batch_stage_kernel(const SlotRec *sl
         a.in64 = s == 0 ? R.y : (s == 2 ? R.w1 : R.w0);
         a.ybase = R.y;
         a.out64 = s == 3 ? R.y : (s == 1 ? R.w1 : R.w0);
-        if (s == 0) process_tile<M, true, false, BASE_IN, false, true, false>(P, TR, S, a, first);
-        else process_tile<M, true, false, BASE_Y, false, true, false>(P, TR, S, a, first);
+        if (SV == 0) process_tile<M, true, false, BASE_IN, false, true, TOP>(P, TR, S, a, first, &D, lw);
+        else process_tile<M, true, false, BASE_Y, false, true, TOP>(P, TR, S, a, first, &D, lw);
     } else {
         // the state ping-pongs between y and w0 from the first step of the call
         double2 *cur = ((st - 1) & 1) ? R.w0 : R.y, *nxt = ((st - 1) & 1) ? R.y : R.w0;
@@ -665,9 +711,9 @@ __global__ __launch_bounds__(MAX_TILE) void batch_stage_kernel(const SlotRec *sl
         a.ybase = cur;
         a.out32 = s == 1 ? R.u2 : R.u1;
         a.out64 = nxt;
-        if (s == 0) process_tile<M, true, false, BASE_NONE, false, false, false>(P, TR, S, a, false);
-        else if (s < 3) process_tile<M, false, true, BASE_NONE, true, false, false>(P, TR, S, a, false);
-        else process_tile<M, true, true, BASE_Y, false, true, false>(P, TR, S, a, first);
+        if (SV == 0) process_tile<M, true, false, BASE_NONE, false, false, TOP>(P, TR, S, a, false, &D, lw);
+        else if (SV == 1) process_tile<M, false, true, BASE_NONE, true, false, TOP>(P, TR, S, a, false, &D, lw);
+        else process_tile<M, true, true, BASE_Y, false, true, TOP>(P, TR, S, a, first, &D, lw);
     }
 }
 
@@ -785,20 +831,36 @@ int check_dev(const void *p, const char *name) {
     return HEOM_OK;
 }
 
+template <int M, int PREC, bool TOP>
+void batch_launch_group(const heom_batch::Group &g, hipStream_t s, const SlotRec *recs, const BatchTile *first,
+                        int stage, int64_t done, int64_t st, uint32_t policy) {
+    const dim3 grid(g.count), block(g.block);
+    const int sv = stage == 0 ? 0 : (PREC == HEOM_FP64 ? 1 : (stage < 3 ? 1 : 2));
+    if (sv == 0)
+        hipLaunchKernelGGL((batch_stage_kernel<M, PREC, TOP, 0>), grid, block, g.lds, s, recs, first, stage, done, st,
+                           policy);
+    else if (sv == 1)
+        hipLaunchKernelGGL((batch_stage_kernel<M, PREC, TOP, 1>), grid, block, g.lds, s, recs, first, stage, done, st,
+                           policy);
+    else if (PREC == HEOM_FP32)
+        hipLaunchKernelGGL((batch_stage_kernel<M, PREC, TOP, 2>), grid, block, g.lds, s, recs, first, stage, done, st,
+                           policy);
+}
+
 template <int PREC>
 int batch_launch(const heom_batch *b, hipStream_t s, int stage, int64_t st, uint32_t policy) {
     const SlotRec *recs = static_cast<const SlotRec *>(b->dev);
     const size_t tile_off = (sizeof(SlotRec) * b->slots.size() + 255) & ~(size_t)255;
     const BatchTile *tl = reinterpret_cast<const BatchTile *>(static_cast<const unsigned char *>(b->dev) + tile_off);
     for (const auto &g : b->groups) {
-        const BatchTile *first = tl + g.second.first;
-        const dim3 grid(g.second.second), block(b->block);
-#define HEOM_BCASE(MM)                                                                                          \
-    case MM:                                                                                                    \
-        hipLaunchKernelGGL((batch_stage_kernel<MM, PREC>), grid, block, b->lds, s, recs, first, stage,        \
-                           b->steps_since_commit, st, policy);                                                  \
+        const BatchTile *first = tl + g.first;
+        const int64_t done = b->steps_since_commit;
+#define HEOM_BCASE(MM)                                                                              \
+    case MM:                                                                                        \
+        if (g.top) batch_launch_group<MM, PREC, true>(g, s, recs, first, stage, done, st, policy);  \
+        else batch_launch_group<MM, PREC, false>(g, s, recs, first, stage, done, st, policy);       \
         break;
-        switch (g.first) {
+        switch (g.m) {
             HEOM_BCASE(1) HEOM_BCASE(2) HEOM_BCASE(3) HEOM_BCASE(4)
             HEOM_BCASE(5) HEOM_BCASE(6) HEOM_BCASE(7) HEOM_BCASE(8)
             default: return fail(HEOM_E_UNSUPPORTED, "m out of range");
@@ -1226,36 +1288,52 @@ int heom_batch_commit(heom_batch *b, void *dev, size_t bytes, void *stream) {
     SlotRec *recs = reinterpret_cast<SlotRec *>(img.data());
     BatchTile *tl = reinterpret_cast<BatchTile *>(img.data() + tile_off);
     b->groups.clear();
-    b->block = 64;
-    b->lds = 0;
-    size_t k = 0;
-    for (int m = 1; m <= HEOM_MAX_M; ++m) {
-        const size_t first = k;
-        for (size_t i = 0; i < ns; ++i) {
-            const BatchSlotHost &S = b->slots[i];
-            if (!S.used || S.tables->t.m != m) continue;
-            const HostTables &t = S.tables->t;
-            const size_t n = t.n_var;
-            SlotRec &R = recs[i];
-            R.img = static_cast<const unsigned char *>(t.dev);
-            R.params = static_cast<const unsigned char *>(S.params);
-            unsigned char *wb = static_cast<unsigned char *>(S.work);
-            R.y = static_cast<double2 *>(S.y);
-            R.w0 = reinterpret_cast<double2 *>(wb);
-            R.w1 = R.w0 + n;
-            R.u1 = reinterpret_cast<float2 *>(wb + 16 * n);
-            R.u2 = R.u1 + n;
-            R.obs = S.obs;
-            R.obs_every = S.obs_every;
-            R.obs_cap = S.obs_cap;
-            R.step0 = S.steps;
-            R.dt = S.dt;
-            for (uint32_t j = 0; j < t.tiles.size(); ++j) tl[k++] = BatchTile{(uint32_t)i, j};
-            b->block = std::max<uint32_t>(b->block, (uint32_t)t.tile_vars);
-            b->lds = std::max<uint32_t>(b->lds, t.lds_bytes);
-        }
-        if (k > first) b->groups.push_back({m, {(uint32_t)first, (uint32_t)(k - first)}});
+    for (size_t i = 0; i < ns; ++i) {
+        const BatchSlotHost &S = b->slots[i];
+        if (!S.used) continue;
+        const HostTables &t = S.tables->t;
+        const size_t n = t.n_var;
+        SlotRec &R = recs[i];
+        R.img = static_cast<const unsigned char *>(t.dev);
+        R.params = static_cast<const unsigned char *>(S.params);
+        unsigned char *wb = static_cast<unsigned char *>(S.work);
+        R.y = static_cast<double2 *>(S.y);
+        R.w0 = reinterpret_cast<double2 *>(wb);
+        R.w1 = R.w0 + n;
+        R.u1 = reinterpret_cast<float2 *>(wb + 16 * n);
+        R.u2 = R.u1 + n;
+        R.obs = S.obs;
+        R.obs_every = S.obs_every;
+        R.obs_cap = S.obs_cap;
+        R.step0 = S.steps;
+        R.dt = S.dt;
     }
+    // Group the tiles by (m, tile size, tier class); within a group, slot by
+    // slot in slot order and each slot's tiles in order.
+    std::vector<int> sizes;
+    for (const auto &S : b->slots)
+        if (S.used) sizes.push_back(S.tables->t.tile_vars);
+    std::sort(sizes.begin(), sizes.end());
+    sizes.erase(std::unique(sizes.begin(), sizes.end()), sizes.end());
+    size_t k = 0;
+    for (int m = 1; m <= HEOM_MAX_M; ++m)
+        for (int tv : sizes)
+            for (int top = 0; top < 2; ++top) {
+                const size_t first = k;
+                uint32_t lds = 0;
+                for (size_t i = 0; i < ns; ++i) {
+                    const BatchSlotHost &S = b->slots[i];
+                    if (!S.used || S.tables->t.m != m || S.tables->t.tile_vars != tv) continue;
+                    const HostTables &t = S.tables->t;
+                    const uint32_t T = (uint32_t)t.tiles.size();
+                    const uint32_t split = (t.top_tile > 0 && t.top_tile < T) ? t.top_tile : T;
+                    const uint32_t j0 = top ? split : 0, j1 = top ? T : split;
+                    for (uint32_t j = j0; j < j1; ++j) tl[k++] = BatchTile{(uint32_t)i, j};
+                    if (j1 > j0) lds = std::max<uint32_t>(lds, t.lds_bytes);
+                }
+                if (k > first)
+                    b->groups.push_back({m, top != 0, (uint32_t)tv, lds, (uint32_t)first, (uint32_t)(k - first)});
+            }
     hipStream_t s = static_cast<hipStream_t>(stream);
     HIP_TRY(hipMemcpyAsync(dev, img.data(), need, hipMemcpyHostToDevice, s));
     // Row 0 of a new slot's observables: the initial state, evaluated with

@@ -498,6 +498,8 @@ int make_tiles(HostTables *t, int tile_vars, std::string *err) {
         for (uint32_t p = r.p0; p < r.p0 + r.np; ++p) expand_gathers(*t, p, &t->gidx);
         if (t->gidx.size() > 0xffffffffull) { *err = "more than 2^32-1 hierarchy gathers"; return HEOM_E_TOO_LARGE; }
         r.ng = (uint32_t)t->gidx.size() - r.g0;
+        // each tile's list starts on a 16-byte boundary (staged as 16-byte words)
+        while (t->gidx.size() % 4) t->gidx.push_back(0u);
         t->max_np = std::max(t->max_np, r.np);
         t->max_nc = std::max(t->max_nc, r.nc);
         t->max_ng = std::max(t->max_ng, r.ng);

@@ -291,7 +291,7 @@ class Server:
         free_slots = {l.index: (len(l.free) if lane_idle[l.index] else 0) for l in self.lanes}
         if not self.waiting or not any(free_slots[i] > 0 and self.waiting_per_lane[i] > 0 for i in free_slots):
             return
-        waiting = [(w[0].rid, w[1], w[2], w[3]) for w in self.waiting]
+        waiting = ((w[0].rid, w[1], w[2], w[3]) for w in self.waiting)   # lazily: admission stops early
         resident = {k: s.table_bytes for k, s in self.structs.items() if s.image is not None}
         evictable = sorted((k for k, s in self.structs.items() if s.image is not None and s.users == 0),
                            key=lambda k: self.structs[k].last_use)
@@ -417,28 +417,28 @@ class Server:
                 progressed = True
         return progressed
 
-    def run(self, requests: Sequence[Request], stop_at: Optional[float] = None,
-            drain: bool = True) -> Dict:
+    def run(self, requests: Sequence[Request], window: Optional[float] = None,
+            deadline: Optional[float] = None) -> Dict:
         """Replay a trace: each request is submitted at its arrival time
-        (seconds from the start). Runs until every request completes, or,
-        with stop_at, submits only arrivals up to stop_at seconds and, with
-        drain=False, abandons what is still waiting or in flight then
-        (reported as outstanding). Returns summary statistics; per-request
-        results are in self.results."""
-        reqs = sorted(requests, key=lambda r: r.arrival)
+        (seconds from the start). Only arrivals up to `window` seconds are
+        submitted (all when None). The run ends when every submitted request
+        has completed or, if given, at `deadline` seconds; what is then
+        still waiting or in flight is reported as outstanding. Returns
+        summary statistics; per-request results are in self.results."""
+        reqs = [r for r in sorted(requests, key=lambda r: r.arrival) if window is None or r.arrival <= window]
         self.t0 = self._clock()
         i = 0
         submitted = 0
         while True:
             now = self.now()
-            while i < len(reqs) and reqs[i].arrival <= now and (stop_at is None or reqs[i].arrival <= stop_at):
+            while i < len(reqs) and reqs[i].arrival <= now:
                 submitted += int(self.submit(reqs[i]))
                 i += 1
-            more = i < len(reqs) and (stop_at is None or reqs[i].arrival <= stop_at)
+            more = i < len(reqs)
             busy = self.in_flight() > 0 or bool(self.waiting)
             if not more and not busy:
                 break
-            if stop_at is not None and now > stop_at and not drain:
+            if deadline is not None and now > deadline:
                 break
             if not self.poll():
                 if not busy and more:
@@ -488,7 +488,8 @@ class Fifo:
             self.structs[key] = T
         return T
 
-    def solve(self, req: Request, stop_at: Optional[float] = None) -> Optional[np.ndarray]:
+    def solve(self, req: Request, deadline: Optional[float] = None) -> Optional[np.ndarray]:
+        """One request start to finish; None if the deadline passed first."""
         torch = self.torch
         s = torch.cuda.current_stream()
         T = self._tables(req.problem)
@@ -503,44 +504,42 @@ class Fifo:
         every = req.obs_every
         nobs = req.horizon // every + 1 if every > 0 else 1
         obs = torch.zeros(nobs * heom.HEOM_NOBS, dtype=torch.float64, device="cuda")
-        step = self.chunk - self.chunk % every if every > 0 else self.chunk
-        step = max(step, every if every > 0 else 1)
+        step = max(self.chunk - self.chunk % every, every) if every > 0 else self.chunk
         done = 0
         while done < req.horizon:
             k = min(step, req.horizon - done)
             view = obs[(done // every) * heom.HEOM_NOBS:] if every > 0 else None
             T.propagate(y, work, req.dt, k, every, view, self.precision, s)
             done += k
-            if stop_at is not None and done < req.horizon:
+            if deadline is not None and done < req.horizon:
                 torch.cuda.synchronize()
-                if self.now() > stop_at:
+                if self.now() > deadline:
                     return None
         return obs.cpu().numpy().reshape(-1, heom.HEOM_NOBS)
 
-    def run(self, requests: Sequence[Request], stop_at: Optional[float] = None, drain: bool = True) -> Dict:
-        reqs = sorted(requests, key=lambda r: r.arrival)
+    def run(self, requests: Sequence[Request], window: Optional[float] = None,
+            deadline: Optional[float] = None) -> Dict:
+        """The same trace rules as Server.run."""
+        reqs = [r for r in sorted(requests, key=lambda r: r.arrival) if window is None or r.arrival <= window]
         self.t0 = self._clock()
-        submitted = 0
-        outstanding = 0
+        completed = 0
         for j, r in enumerate(reqs):
-            if stop_at is not None and r.arrival > stop_at:
-                break
-            submitted += 1
             now = self.now()
+            if deadline is not None and max(now, r.arrival) > deadline:
+                break
             if r.arrival > now:
                 time.sleep(r.arrival - now)
-            if stop_at is not None and not drain and self.now() > stop_at:
-                outstanding += 1
-                continue
             start = self.now()
-            obs = self.solve(r, None if drain else stop_at)
+            obs = self.solve(r, deadline)
             if obs is None:
-                outstanding += 1
-                continue
+                break
             T = self.structs[structure_key(r.problem)]
             self.results.append(Result(r.rid, r.arrival, start, self.now(), obs, int(T.info()["n_var"])))
+            completed += 1
         self.torch.cuda.synchronize()
-        return summarize(self.results, submitted, self.now(), outstanding=outstanding)
+        elapsed = self.now()
+        submitted = sum(1 for r in reqs if r.arrival <= elapsed)
+        return summarize(self.results, submitted, elapsed, outstanding=submitted - completed)
 
 
 # --------------------------------------------------------------- statistics
