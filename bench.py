@@ -52,10 +52,11 @@ def stage_bytes_per_var(precision: int):
     once):
       FP64: stage 1 reads y, writes w1 (32); stages 2-4 read w, y, write
             w or y (48 each)                                   -> 176
-      FP32: stage 1 reads y, writes u1 (24); 2 reads u1 writes u2 (16);
-            3 reads u1, u2 writes u3 (24); 4 reads y, u3 writes y' (40) -> 104
+      FP32: stage 1 reads y, writes u1 (24); 2 reads u1, writes u2 (16);
+            3 reads u2, u1, writes u3 (24); 4 reads u3, u1, y, writes y (48)
+                                                               -> 112
     """
-    return 176 if precision == 0 else 104
+    return 176 if precision == 0 else 112
 
 
 def sha256(path):

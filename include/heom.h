@@ -153,10 +153,13 @@ int heom_rhs(const heom_tables *t, const void *y_dev, void *dy_dev, void *stream
  * right-hand-side + combination stages.
  *   precision HEOM_FP64: all stages in complex FP64; work_dev holds
  *     work_bytes_fp64 bytes (two state vectors).
- *   precision HEOM_FP32: y stays complex FP64; the stage increments are
- *     stored and gathered as complex FP32 while multiplicities, square-root
- *     weights, damping and the combination with y stay FP64;
- *     work_dev holds work_bytes_fp32 bytes.
+ *   precision HEOM_FP32: y stays complex FP64; the increments
+ *     u1 = h/4 M y, u2 = h/3 M (y + u1), u3 = h/2 M (y + u2) are stored as
+ *     complex FP32, and each later stage gathers only its FP32 increment,
+ *     using linearity (M y = (4/h) u1); y += h M (y + u3) is applied in
+ *     place. Multiplicities, square-root weights, damping, the arithmetic
+ *     and the combination with y stay FP64; work_dev holds work_bytes_fp32
+ *     bytes.
  * If obs_every > 0, obs_dev (device, (nsteps/obs_every + 1)*HEOM_NOBS
  * doubles) receives the observables of heom_observables before the first
  * step and after every obs_every steps. obs_dev may be NULL if obs_every is 0.

@@ -540,8 +540,8 @@ __device__ __forceinline__ bool grid_barrier(uint32_t *flags, uint32_t *timeout,
 
 struct PersistArgs {
     double2 *y;         // state (FP64), updated in place
-    double2 *w0, *w1;   // FP64 stage vectors, or y2 (w0) for FP32
-    float2 *u1, *u2;    // FP32 increments
+    double2 *w0, *w1;   // FP64 stage vectors
+    float2 *u1, *u2, *u3;  // FP32 increments
     double dt;
     int64_t step0;      // index of the first step of this launch (for observables)
     int64_t nsteps;
@@ -580,7 +580,6 @@ __global__ __launch_bounds__(MAX_TILE) void persistent_kernel(Dev D, PersistArgs
     const double h = pa.dt;
     const double al[4] = {h / 4.0, h / 3.0, h / 2.0, h};
     uint32_t epoch = 0;
-    double2 *cur = pa.y, *nxt = pa.w0;
     for (int64_t st = 1; st <= pa.nsteps; ++st) {
         const int64_t gst = pa.step0 + st;
         double *ob = (pa.obs != nullptr && pa.obs_every > 0 && gst % pa.obs_every == 0)
@@ -593,13 +592,13 @@ __global__ __launch_bounds__(MAX_TILE) void persistent_kernel(Dev D, PersistArgs
                 a.ybase = pa.y;
                 a.out64 = s == 3 ? pa.y : (s == 1 ? pa.w1 : pa.w0);
             } else {
-                a.in64 = (s == 0 || s == 3) ? cur : nullptr;
-                a.in32 = s == 1 ? pa.u1 : (s == 2 ? pa.u2 : (s == 3 ? pa.u1 : nullptr));
+                a.in64 = s == 0 ? pa.y : nullptr;
+                a.in32 = s == 1 ? pa.u1 : (s == 2 ? pa.u2 : (s == 3 ? pa.u3 : nullptr));
                 a.extra = pa.u1;
                 a.extra_scale = 4.0 / h;
-                a.ybase = cur;
-                a.out32 = s == 1 ? pa.u2 : pa.u1;
-                a.out64 = nxt;
+                a.ybase = pa.y;
+                a.out32 = s == 0 ? pa.u1 : (s == 1 ? pa.u2 : pa.u3);
+                a.out64 = pa.y;
             }
             a.obs = s == 3 ? ob : nullptr;
             a.policy = pa.policy;
@@ -612,21 +611,12 @@ __global__ __launch_bounds__(MAX_TILE) void persistent_kernel(Dev D, PersistArgs
                 } else {
                     if (s == 0) process_tile<M, true, false, BASE_NONE, false, false, false>(P, TR, S, a, false, sd, 0u);
                     else if (s < 3) process_tile<M, false, true, BASE_NONE, true, false, false>(P, TR, S, a, false, sd, 0u);
-                    else process_tile<M, true, true, BASE_Y, false, true, false>(P, TR, S, a, tl == 0, sd, 0u);
+                    else process_tile<M, false, true, BASE_Y, true, true, false>(P, TR, S, a, tl == 0, sd, 0u);
                 }
             }
             epoch += 1;
             if (!grid_barrier(pa.flags, pa.timeout, epoch, pa.limit)) return;
         }
-        if (PREC != HEOM_FP64) {
-            double2 *tmp = cur;
-            cur = nxt;
-            nxt = tmp;
-        }
-    }
-    if (PREC != HEOM_FP64 && cur != pa.y) {
-        // an odd number of steps leaves the state in the second buffer
-        for (uint32_t i = w * blockDim.x + threadIdx.x; i < P.n_var; i += W * blockDim.x) pa.y[i] = cur[i];
     }
 }
 
@@ -637,8 +627,8 @@ __global__ __launch_bounds__(MAX_TILE) void persistent_kernel(Dev D, PersistArgs
 struct SlotRec {
     const unsigned char *img;
     const unsigned char *params;
-    double2 *y, *w0, *w1;     // FP64 stage vectors (FP32: w0 = second state buffer)
-    float2 *u1, *u2;          // FP32 increments
+    double2 *y, *w0, *w1;     // FP64 stage vectors
+    float2 *u1, *u2, *u3;     // FP32 increments
     double *obs;
     int64_t obs_every, obs_cap, step0;
     double dt;
@@ -675,6 +665,7 @@ __global__ __launch_bounds__(MAX_TILE) void batch_stage_kernel(const SlotRec *sl
     R.w1 = as_global(R.w1);
     R.u1 = as_global(R.u1);
     R.u2 = as_global(R.u2);
+    R.u3 = as_global(R.u3);
     R.obs = as_global(R.obs);
     const InstParams &P = *reinterpret_cast<const InstParams *>(R.params);
     Dev D;
@@ -702,18 +693,16 @@ __global__ __launch_bounds__(MAX_TILE) void batch_stage_kernel(const SlotRec *sl
         if (SV == 0) process_tile<M, true, false, BASE_IN, false, true, TOP>(P, TR, S, a, first, &D, lw);
         else process_tile<M, true, false, BASE_Y, false, true, TOP>(P, TR, S, a, first, &D, lw);
     } else {
-        // the state ping-pongs between y and w0 from the first step of the call
-        double2 *cur = ((st - 1) & 1) ? R.w0 : R.y, *nxt = ((st - 1) & 1) ? R.y : R.w0;
-        a.in64 = cur;
-        a.in32 = s == 1 ? R.u1 : (s == 2 ? R.u2 : R.u1);
+        a.in64 = R.y;
+        a.in32 = s == 1 ? R.u1 : (s == 2 ? R.u2 : R.u3);
         a.extra = R.u1;
         a.extra_scale = 4.0 / h;
-        a.ybase = cur;
-        a.out32 = s == 1 ? R.u2 : R.u1;
-        a.out64 = nxt;
+        a.ybase = R.y;
+        a.out32 = s == 0 ? R.u1 : (s == 1 ? R.u2 : R.u3);
+        a.out64 = R.y;
         if (SV == 0) process_tile<M, true, false, BASE_NONE, false, false, TOP>(P, TR, S, a, false, &D, lw);
         else if (SV == 1) process_tile<M, false, true, BASE_NONE, true, false, TOP>(P, TR, S, a, false, &D, lw);
-        else process_tile<M, true, true, BASE_Y, false, true, TOP>(P, TR, S, a, first, &D, lw);
+        else process_tile<M, false, true, BASE_Y, true, true, TOP>(P, TR, S, a, first, &D, lw);
     }
 }
 
@@ -728,11 +717,6 @@ __global__ void observables_kernel(Dev D, const double2 *y, double *obs) {
 __global__ void zero_kernel(double2 *y, uint32_t n) {
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
         y[i] = make_double2(0.0, 0.0);
-}
-
-__global__ void copy_kernel(const double2 *src, double2 *dst, uint32_t n) {
-    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
-        dst[i] = src[i];
 }
 
 template <int M, bool HAS64, bool HAS32, int BASE, bool EXTRA, bool OUT64>
@@ -1047,7 +1031,7 @@ int heom_propagate(const heom_tables *h, void *y_dev, void *work_dev, size_t wor
         pa.w0 = reinterpret_cast<double2 *>(wb);
         pa.w1 = pa.w0 + n;
     } else {
-        pa.w0 = reinterpret_cast<double2 *>(wb);
+        pa.u3 = reinterpret_cast<float2 *>(wb);
         pa.u1 = reinterpret_cast<float2 *>(wb + 16 * n);
         pa.u2 = pa.u1 + n;
     }
@@ -1077,25 +1061,23 @@ int heom_propagate(const heom_tables *h, void *y_dev, void *work_dev, size_t wor
             if ((rc = launch_stage<true, false, BASE_Y, false, true>(t, s, a))) return rc;
         }
     } else {
-        double2 *cur = y, *nxt = pa.w0;
-        float2 *u1 = pa.u1, *u2 = pa.u2;
+        // u1 = h/4 M y, u2 = h/3 M (y + u1), u3 = h/2 M (y + u2) and
+        // y += h M (y + u3), each from the FP32 increment it gathers plus
+        // M y = (4/h) u1; the state is updated in place by its owner.
+        float2 *u1 = pa.u1, *u2 = pa.u2, *u3 = pa.u3;
         const double inv_h1 = 1.0 / h1;
         for (int64_t st = 1; st <= nsteps; ++st) {
             double *ob = (obs_every > 0 && st % obs_every == 0) ? obs_dev + (st / obs_every) * HEOM_NOBS : nullptr;
             StageArgs a{};
-            a.in64 = cur; a.out32 = u1; a.alpha = h1;
+            a.in64 = y; a.out32 = u1; a.alpha = h1;
             if ((rc = launch_stage<true, false, BASE_NONE, false, false>(t, s, a))) return rc;
             a = StageArgs{}; a.in32 = u1; a.extra = u1; a.extra_scale = inv_h1; a.out32 = u2; a.alpha = h2;
             if ((rc = launch_stage<false, true, BASE_NONE, true, false>(t, s, a))) return rc;
-            a = StageArgs{}; a.in32 = u2; a.extra = u1; a.extra_scale = inv_h1; a.out32 = u1; a.alpha = h3;
+            a = StageArgs{}; a.in32 = u2; a.extra = u1; a.extra_scale = inv_h1; a.out32 = u3; a.alpha = h3;
             if ((rc = launch_stage<false, true, BASE_NONE, true, false>(t, s, a))) return rc;
-            a = StageArgs{}; a.in64 = cur; a.in32 = u1; a.ybase = cur; a.out64 = nxt; a.alpha = h4; a.obs = ob;
-            if ((rc = launch_stage<true, true, BASE_Y, false, true>(t, s, a))) return rc;
-            std::swap(cur, nxt);
-        }
-        if (cur != y) {
-            hipLaunchKernelGGL(copy_kernel, dim3(1024), dim3(256), 0, s, cur, y, t.n_var);
-            HIP_TRY(hipGetLastError());
+            a = StageArgs{}; a.in32 = u3; a.extra = u1; a.extra_scale = inv_h1; a.ybase = y; a.out64 = y;
+            a.alpha = h4; a.obs = ob;
+            if ((rc = launch_stage<false, true, BASE_Y, true, true>(t, s, a))) return rc;
         }
     }
     return HEOM_OK;
@@ -1302,6 +1284,7 @@ int heom_batch_commit(heom_batch *b, void *dev, size_t bytes, void *stream) {
         R.w1 = R.w0 + n;
         R.u1 = reinterpret_cast<float2 *>(wb + 16 * n);
         R.u2 = R.u1 + n;
+        R.u3 = reinterpret_cast<float2 *>(wb);
         R.obs = S.obs;
         R.obs_every = S.obs_every;
         R.obs_cap = S.obs_cap;
@@ -1366,14 +1349,6 @@ int heom_batch_propagate(heom_batch *b, int64_t nsteps, int precision, void *str
                                             : batch_launch<HEOM_FP32>(b, s, stage, st, policy);
             if (rc) return rc;
         }
-    if (precision == HEOM_FP32 && (nsteps & 1)) {
-        for (const auto &S : b->slots) {
-            if (!S.used) continue;
-            hipLaunchKernelGGL(copy_kernel, dim3(256), dim3(256), 0, s, static_cast<const double2 *>(S.work),
-                               static_cast<double2 *>(S.y), S.tables->t.n_var);
-            HIP_TRY(hipGetLastError());
-        }
-    }
     b->steps_since_commit += nsteps;
     for (auto &S : b->slots)
         if (S.used) S.steps += nsteps;
