@@ -73,6 +73,7 @@ struct Dev {
     const CatRec *cat;
     const uint32_t *gidx;
     const TileRec *tiles;
+    const VarRec *vrec;
 };
 
 Dev dev_view(const HostTables &t) {
@@ -85,6 +86,7 @@ Dev dev_view(const HostTables &t) {
     D.cat = reinterpret_cast<const CatRec *>(b + ip->off_cat);
     D.gidx = reinterpret_cast<const uint32_t *>(b + ip->off_gidx);
     D.tiles = reinterpret_cast<const TileRec *>(b + ip->off_tile);
+    D.vrec = reinterpret_cast<const VarRec *>(b + ip->off_vrec);
     return D;
 }
 
@@ -100,31 +102,6 @@ __device__ __forceinline__ void cfma(double2 &acc, double2 w, double2 v) {
     acc.x += w.x * v.x - w.y * v.y;
     acc.y += w.x * v.y + w.y * v.x;
 }
-
-// ------------------------------------------------------------ input views
-struct InF64 {
-    const double2 *a;
-    __device__ __forceinline__ double2 load(uint32_t j) const { return a[j]; }
-};
-struct InF32 {
-    const float2 *b;
-    __device__ __forceinline__ double2 load(uint32_t j) const {
-        float2 v = b[j];
-        return make_double2((double)v.x, (double)v.y);
-    }
-};
-struct InSum {  // y + u with y complex FP64 and u complex FP32
-    const double2 *a;
-    const float2 *b;
-    __device__ __forceinline__ double2 load(uint32_t j) const {
-        double2 y = a[j];
-        float2 u = b[j];
-        return make_double2(y.x + (double)u.x, y.y + (double)u.y);
-    }
-};
-
-__device__ __forceinline__ void store(double2 *p, double2 v) { *p = v; }
-__device__ __forceinline__ void store(float2 *p, double2 v) { *p = make_float2((float)v.x, (float)v.y); }
 
 // blockIdx -> tile such that each of the 8 XCDs (workgroups are dealt to
 // XCDs round robin) processes one contiguous run of tiles.
@@ -218,6 +195,7 @@ enum { BASE_NONE = 0, BASE_IN = 1, BASE_Y = 2 };
 // connection records, coefficient tables.
 struct Smem {
     double2 *val;
+    double2 *rc;      // grouped sums of the tile's blocks (see process_tile)
     PatHdr *hdr;
     CatRec *cat;
     uint32_t *gix;
@@ -227,7 +205,8 @@ struct Smem {
 __device__ __forceinline__ Smem carve(unsigned char *smem, const InstParams &P) {
     Smem S;
     S.val = reinterpret_cast<double2 *>(smem);
-    S.hdr = reinterpret_cast<PatHdr *>(smem + 16u * P.tile_vars);
+    S.rc = S.val + P.tile_vars;
+    S.hdr = reinterpret_cast<PatHdr *>(smem + 32u * P.tile_vars);
     S.cat = reinterpret_cast<CatRec *>(S.hdr + P.max_np);
     S.gix = reinterpret_cast<uint32_t *>(S.cat + P.max_nc);
     S.lut = reinterpret_cast<double *>(S.gix + ((P.max_ng + 3u) & ~3u));
@@ -266,24 +245,6 @@ __device__ __forceinline__ void stage_tile(const Dev &D, const TileRec &TR, cons
     }
 }
 
-// Exclusive prefix sum of x over the threads of the workgroup (thread order).
-__device__ __forceinline__ uint32_t wg_exclusive_scan(uint32_t x) {
-    __shared__ uint32_t wsum[MAX_TILE / 64];
-    const uint32_t lane = threadIdx.x & 63u, wid = threadIdx.x >> 6;
-    uint32_t v = x;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        const uint32_t y = __shfl_up(v, d, 64);
-        if (lane >= (uint32_t)d) v += y;
-    }
-    if (lane == 63u) wsum[wid] = v;
-    __syncthreads();
-    uint32_t base = 0;
-    for (uint32_t w = 0; w < wid; ++w) base += wsum[w];
-    __syncthreads();
-    return base + v - x;
-}
-
 // 16-byte words of the coefficient tables (2 m (L+1) doubles).
 __device__ __forceinline__ uint32_t lut_words(const InstParams &P) { return (uint32_t)P.m * (uint32_t)(P.L + 1); }
 
@@ -304,16 +265,6 @@ __device__ __forceinline__ double2 load_in(const StageArgs &a, uint32_t j) {
     return v;
 }
 
-// One fused stage over one tile. The tile's metadata and the coefficient
-// tables are staged into LDS first (stage_tile), unless `stage` is NULL and
-// they are there already.
-//
-// Every variable has up to 4M hierarchy gathers ("slots"): for each channel
-// k, the row molecule raised (k), lowered (M+k), the column molecule raised
-// (2M+k), lowered (3M+k) (Eqs. uvar-up, uvar-down). Their target indices
-// come from the LDS connection records alone, so all of a thread's gathers
-// are issued together with its own-value load, before the workgroup barrier
-// that publishes the tile's values for the grouped sums.
 template <bool HAS64, bool HAS32>
 __device__ __forceinline__ double2 load_own(const StageArgs &a, uint32_t j) {
     if (!(a.policy & 1u)) return load_in<HAS64, HAS32>(a, j);
@@ -327,65 +278,56 @@ __device__ __forceinline__ double2 load_own(const StageArgs &a, uint32_t j) {
     return v;
 }
 
+// One fused stage over one tile, one thread per unique variable.
+//
+// 1. The thread's own loads (its decode record, input value, base and extra
+//    terms) go out first and stay in flight while the tile's metadata and
+//    coefficient tables are staged into LDS (stage_tile; skipped when
+//    `stage` is false and they are there already). Barriers wait for LDS
+//    traffic only.
+// 2. Every variable has up to 4M hierarchy gathers ("slots"): for each
+//    channel k, the row molecule raised (k), lowered (M+k), the column
+//    molecule raised (2M+k), lowered (3M+k) (Eqs. uvar-up, uvar-down). The
+//    record names the live slots and where their target indices sit in the
+//    tile's list; the gathers are issued together and their weighted sum is
+//    formed before the barrier that publishes the tile's values.
+// 3. Grouped sums (Eqs. grouped-row-sum, grouped-column-sum, HZ): in each
+//    block, the thread at position l < 2G+1 forms one of them -- l = 0 the
+//    Z bracket sum_q M_q (X_q - Y_q), l = 1..G the row sum R_{l-1}, l =
+//    G+1..2G the column sum C_{l-1-G} -- into LDS, so the loops over the
+//    block's categories run on a few lanes instead of on every lane.
+// 4. Every thread reads its Hamiltonian bracket from LDS, adds damping,
+//    loss, the terminator and the extra term, and writes the combination.
 template <int M, bool HAS64, bool HAS32, int BASE, bool EXTRA, bool OUT64, bool TOP>
-__device__ __forceinline__ void process_tile(const InstParams &P, const TileRec &TR, const Smem &S,
-                                             const StageArgs &a, bool first_tile, const Dev *stage,
-                                             uint32_t lut_w) {
+__device__ __forceinline__ void process_tile(const InstParams &P, const Dev &D, const TileRec &TR, const Smem &S,
+                                             const StageArgs &a, bool first_tile, bool stage, uint32_t lut_w) {
     const uint32_t t = threadIdx.x;
     const bool active = t < TR.nv;
-    // The loads that depend on the thread alone go out first and stay in
-    // flight while the tile's metadata is staged (the barriers below wait
-    // for LDS traffic only).
     double2 own = make_double2(0.0, 0.0), ybv = make_double2(0.0, 0.0);
     float2 ex = make_float2(0.0f, 0.0f);
+    VarRec vr{0u, 0u};
     if (active) {
+        vr = D.vrec[TR.v0 + t];
         own = load_own<HAS64, HAS32>(a, TR.v0 + t);
         if (BASE == BASE_Y) ybv = (a.policy & 2u) ? ld_stream(a.ybase + TR.v0 + t) : a.ybase[TR.v0 + t];
         if (EXTRA) ex = a.extra[TR.v0 + t];
     }
-    if (stage != nullptr) stage_tile(*stage, TR, S, lut_w);
+    if (stage) stage_tile(D, TR, S, lut_w);
     __syncthreads();
-    int kind = KIND_Z, A = 0, B = 0, q = 0, r = 0;
-    uint32_t base = 0, lo = 0;
-    PatHdr H{};
-    CatRec cq{}, cr2{};
-    bool chi = false;
-    uint32_t idx[4 * M];
-    uint32_t live = 0;
-    double2 v[4 * M];
+
+    const uint32_t p = vr.x & 127u, A = (vr.x >> 7) & 31u, B = (vr.x >> 12) & 31u;
+    const bool isT = (vr.x >> 17) & 1u;
+    const uint32_t goff = vr.x >> 18, live = vr.y;
+    const PatHdr H = S.hdr[p];
+    const uint32_t base = H.off - TR.v0, loc = t - base;
+    const int G = H.G, G1 = G + 1, nm = G1 * G1;
+    const int kind = (A == 0 && B == 0) ? KIND_Z : (B == 0 ? KIND_X : (A == 0 ? KIND_Y : ((A == B && !isT) ? KIND_P : KIND_S)));
+    const CatRec *cats = S.cat + (H.cat_base - TR.c0);
     double2 hier = make_double2(0.0, 0.0);
     if (active) {
-        uint32_t hi = TR.np;  // block lo holds variable t
-        while (hi - lo > 1) {
-            uint32_t mid = (lo + hi) >> 1;
-            if (S.hdr[mid].off - TR.v0 <= t) lo = mid; else hi = mid;
-        }
-        H = S.hdr[lo];
-        base = H.off - TR.v0;
-        const uint32_t loc = t - base;
-        const int G1 = H.G + 1, nm = G1 * G1;
-        bool isT = false;
-        if (loc < (uint32_t)nm) {
-            A = (int)loc / G1;
-            B = (int)loc - A * G1;
-        } else {
-            uint32_t mask = H.tmask;
-            for (int s = (int)loc - nm; s > 0; --s) mask &= mask - 1u;
-            A = B = __ffs(mask);  // category index + 1
-            isT = true;
-        }
-        kind = (A == 0 && B == 0) ? KIND_Z : (B == 0 ? KIND_X : (A == 0 ? KIND_Y : ((A == B && !isT) ? KIND_P : KIND_S)));
-        q = A - 1;
-        r = B - 1;
-        chi = TOP ? false : (H.tier < P.L);   // the top tier has no up moves
-        const CatRec *cats = S.cat + (H.cat_base - TR.c0);
-        if (A > 0) cq = cats[q];
-        if (B > 0) cr2 = cats[r];
-        live = live_slots(kind, chi, cq.vec, cr2.vec, M);
-    }
-    // position of this variable's gather indices in the tile's list
-    const uint32_t goff = wg_exclusive_scan(__popc(live));
-    if (active) {
+        const CatRec cq = A > 0 ? cats[A - 1] : CatRec{}, cr2 = B > 0 ? cats[B - 1] : CatRec{};
+        uint32_t idx[4 * M];
+        double2 v[4 * M];
 #pragma unroll
         for (int j = 0; j < 4 * M; ++j) {
             const bool up_slot = ((j / M) & 1) == 0;   // slots 0..M-1 and 2M..3M-1 are up moves
@@ -397,9 +339,8 @@ __device__ __forceinline__ void process_tile(const InstParams &P, const TileRec 
             v[j] = (!(TOP && up_slot) && ((live >> j) & 1u)) ? load_in<HAS64, HAS32>(a, idx[j]) : make_double2(0.0, 0.0);
         }
         S.val[t] = own;
-        // hierarchy: row moves -i sqrt((n+1)|c|), -i sqrt(n/|c|) c_k (P: c_k - cc_k);
-        // column moves +i sqrt((n+1)|c|), +i sqrt(n/|c|) cc_k. Summed before the
-        // barrier, so the gathered values are dead during the grouped sums.
+        // row moves -i sqrt((n+1)|c|), -i sqrt(n/|c|) c_k (P: c_k - cc_k);
+        // column moves +i sqrt((n+1)|c|), +i sqrt(n/|c|) cc_k
         const int L1 = P.L + 1;
         const double *up = S.lut;
         const double *dn = S.lut + M * L1;
@@ -417,47 +358,54 @@ __device__ __forceinline__ void process_tile(const InstParams &P, const TileRec 
     }
     __syncthreads();
 
+    auto mult = [&](int c) -> double {
+        const CatRec cc = cats[c];
+        return (cc.flags & CAT_ZERO) ? (P.npool - (double)H.r) : (double)cc.mult;
+    };
+    if (active && loc < (uint32_t)(2 * G + 1)) {
+        const bool isZ = loc == 0, isRow = loc <= (uint32_t)G;
+        const int c = isZ ? -1 : (isRow ? (int)loc - 1 : (int)loc - 1 - G);
+        double2 sum = make_double2(0.0, 0.0);
+        if (!isZ) {
+            sum = S.val[base + (c + 1) * G1 + c + 1];
+            if ((H.tmask >> c) & 1u)
+                sum = cadd(sum, cscale(mult(c) - 1.0, S.val[base + nm + __popc(H.tmask & ((1u << c) - 1u))]));
+        }
+        for (int x = 0; x < G; ++x) {
+            if (x == c) continue;
+            const int ia = isZ ? (x + 1) * G1 : (isRow ? (c + 1) * G1 + x + 1 : (x + 1) * G1 + c + 1);
+            double2 w = S.val[base + ia];
+            if (isZ) w = csub(w, S.val[base + x + 1]);
+            sum = cadd(sum, cscale(mult(x), w));
+        }
+        S.rc[base + loc] = sum;
+    }
+    __syncthreads();
+
     double2 res = make_double2(0.0, 0.0);
     if (active) {
-        const int G = H.G, G1 = G + 1, nm = G1 * G1;
-        const CatRec *cats = S.cat + (H.cat_base - TR.c0);
-        auto mult = [&](int c) -> double {
-            const CatRec cc = cats[c];
-            return (cc.flags & CAT_ZERO) ? (P.npool - (double)H.r) : (double)cc.mult;
-        };
-        auto sv = [&](int x, int y) { return S.val[base + x * G1 + y]; };
-        auto svT = [&](int c) { return S.val[base + nm + __popc(H.tmask & ((1u << c) - 1u))]; };
+        // Hamiltonian bracket (multiplied by -i g below):
+        //   Z: sum_q M_q (X_q - Y_q)   X_q: Z - R_q   Y_r: C_r - Z
+        //   P_q: Y_q - X_q             S_qr, T_q: Y_r - X_q
+        const double2 *VR = S.val;   // S.rc follows S.val: index tile_vars + i is rc[i]
+        const uint32_t tv = P.tile_vars;
+        uint32_t i1, i2;
+        if (kind == KIND_Z) { i1 = tv + base; i2 = base; }
+        else if (kind == KIND_X) { i1 = base; i2 = tv + base + A; }
+        else if (kind == KIND_Y) { i1 = tv + base + G + B; i2 = base; }
+        else { i1 = base + B; i2 = base + A * G1; }
+        const double2 h1 = VR[i1], h2 = kind == KIND_Z ? make_double2(0.0, 0.0) : VR[i2];
+        const double2 hsum = csub(h1, h2);
         double gam = 0.0;
 #pragma unroll
         for (int k = 0; k < M; ++k) gam += P.nu[k] * (double)vbyte(H.cnt, k);
-        double2 acc, hsum;  // hsum: Hamiltonian bracket, multiplied by -i g below
-        if (kind == KIND_Z) {
-            // Z: -i g sum_q M_q (X_q - Y_q) - (Gamma + kappa) Z   (Eq. HZ)
-            hsum = make_double2(0, 0);
-            for (int c = 0; c < G; ++c) hsum = cadd(hsum, cscale(mult(c), csub(sv(c + 1, 0), sv(0, c + 1))));
-            acc = cscale(-(gam + P.kappa), own);
-        } else if (kind == KIND_X || kind == KIND_Y) {
-            // X_q: -i delta X - i g (Z - R_q) - (Gamma + kappa/2 + Delta) X   (Eq. HX)
-            // Y_q: +i delta Y - i g (C_q - Z) - (Gamma + kappa/2 + Delta) Y
-            const bool isX = kind == KIND_X;
-            const int c = isX ? q : r;
-            double2 R = sv(c + 1, c + 1);
-            if ((H.tmask >> c) & 1u) R = cadd(R, cscale(mult(c) - 1.0, svT(c)));
-            for (int x = 0; x < G; ++x)
-                if (x != c) R = cadd(R, cscale(mult(x), isX ? sv(c + 1, x + 1) : sv(x + 1, c + 1)));
-            hsum = isX ? csub(sv(0, 0), R) : csub(R, sv(0, 0));
-            const double re = -(gam + 0.5 * P.kappa + P.term);
-            const double dl = isX ? P.delta : -P.delta;
-            acc = make_double2(re * own.x + dl * own.y, re * own.y - dl * own.x);
-        } else if (kind == KIND_P) {
-            // P_q: -i g (Y_q - X_q) - Gamma P
-            hsum = csub(sv(0, A), sv(A, 0));
-            acc = cscale(-gam, own);
-        } else {
-            // S_{q,r} or T_q: -i g (Y_r - X_q) - (Gamma + 2 Delta) V
-            hsum = csub(sv(0, B), sv(A, 0));
-            acc = cscale(-(gam + 2.0 * P.term), own);
-        }
+        // diagonal: Z -(Gamma + kappa); X, Y -(Gamma + kappa/2 + Delta) -/+ i delta;
+        // P -Gamma; S, T -(Gamma + 2 Delta)
+        const double re = kind == KIND_Z ? -(gam + P.kappa)
+                          : (kind == KIND_X || kind == KIND_Y) ? -(gam + 0.5 * P.kappa + P.term)
+                          : (kind == KIND_P ? -gam : -(gam + 2.0 * P.term));
+        const double dl = kind == KIND_X ? P.delta : (kind == KIND_Y ? -P.delta : 0.0);
+        double2 acc = make_double2(re * own.x + dl * own.y, re * own.y - dl * own.x);
         acc = cadd(acc, hier);
         acc.x += P.g * hsum.y;
         acc.y -= P.g * hsum.x;
@@ -497,7 +445,7 @@ __global__ __launch_bounds__(MAX_TILE) void stage_kernel(Dev D, StageArgs a, int
     const Smem S = carve(smem, P);
     const uint32_t tile = a.tile0 + (xcd ? xcd_tile(blockIdx.x, gridDim.x) : blockIdx.x);
     const TileRec TR = D.tiles[tile];
-    process_tile<M, HAS64, HAS32, BASE, EXTRA, OUT64, TOP>(P, TR, S, a, tile == 0, &D, lut_words(P));
+    process_tile<M, HAS64, HAS32, BASE, EXTRA, OUT64, TOP>(P, D, TR, S, a, tile == 0, true, lut_words(P));
 }
 
 // Grid-wide barrier for the persistent kernel. Workgroup w publishes its
@@ -604,14 +552,14 @@ __global__ __launch_bounds__(MAX_TILE) void persistent_kernel(Dev D, PersistArgs
             a.policy = pa.policy;
             for (uint32_t tl = t_lo + j; tl < t_hi; tl += wx) {
                 const TileRec TR = single ? TR0 : D.tiles[tl];
-                const Dev *sd = single ? nullptr : &D;   // one tile per workgroup: staged once above
+                const bool sd = !single;   // one tile per workgroup: staged once above
                 if (PREC == HEOM_FP64) {
-                    if (s == 0) process_tile<M, true, false, BASE_IN, false, true, false>(P, TR, S, a, tl == 0, sd, 0u);
-                    else process_tile<M, true, false, BASE_Y, false, true, false>(P, TR, S, a, tl == 0, sd, 0u);
+                    if (s == 0) process_tile<M, true, false, BASE_IN, false, true, false>(P, D, TR, S, a, tl == 0, sd, 0u);
+                    else process_tile<M, true, false, BASE_Y, false, true, false>(P, D, TR, S, a, tl == 0, sd, 0u);
                 } else {
-                    if (s == 0) process_tile<M, true, false, BASE_NONE, false, false, false>(P, TR, S, a, false, sd, 0u);
-                    else if (s < 3) process_tile<M, false, true, BASE_NONE, true, false, false>(P, TR, S, a, false, sd, 0u);
-                    else process_tile<M, false, true, BASE_Y, true, true, false>(P, TR, S, a, tl == 0, sd, 0u);
+                    if (s == 0) process_tile<M, true, false, BASE_NONE, false, false, false>(P, D, TR, S, a, false, sd, 0u);
+                    else if (s < 3) process_tile<M, false, true, BASE_NONE, true, false, false>(P, D, TR, S, a, false, sd, 0u);
+                    else process_tile<M, false, true, BASE_Y, true, true, false>(P, D, TR, S, a, tl == 0, sd, 0u);
                 }
             }
             epoch += 1;
@@ -675,6 +623,7 @@ __global__ __launch_bounds__(MAX_TILE) void batch_stage_kernel(const SlotRec *sl
     D.cat = reinterpret_cast<const CatRec *>(R.img + P.off_cat);
     D.gidx = reinterpret_cast<const uint32_t *>(R.img + P.off_gidx);
     D.tiles = reinterpret_cast<const TileRec *>(R.img + P.off_tile);
+    D.vrec = reinterpret_cast<const VarRec *>(R.img + P.off_vrec);
     const Smem S = carve(smem, P);
     const TileRec TR = D.tiles[B.tile];
     const uint32_t lw = lut_words(P);
@@ -690,8 +639,8 @@ __global__ __launch_bounds__(MAX_TILE) void batch_stage_kernel(const SlotRec *sl
         a.in64 = s == 0 ? R.y : (s == 2 ? R.w1 : R.w0);
         a.ybase = R.y;
         a.out64 = s == 3 ? R.y : (s == 1 ? R.w1 : R.w0);
-        if (SV == 0) process_tile<M, true, false, BASE_IN, false, true, TOP>(P, TR, S, a, first, &D, lw);
-        else process_tile<M, true, false, BASE_Y, false, true, TOP>(P, TR, S, a, first, &D, lw);
+        if (SV == 0) process_tile<M, true, false, BASE_IN, false, true, TOP>(P, D, TR, S, a, first, true, lw);
+        else process_tile<M, true, false, BASE_Y, false, true, TOP>(P, D, TR, S, a, first, true, lw);
     } else {
         a.in64 = R.y;
         a.in32 = s == 1 ? R.u1 : (s == 2 ? R.u2 : R.u3);
@@ -700,9 +649,9 @@ __global__ __launch_bounds__(MAX_TILE) void batch_stage_kernel(const SlotRec *sl
         a.ybase = R.y;
         a.out32 = s == 0 ? R.u1 : (s == 1 ? R.u2 : R.u3);
         a.out64 = R.y;
-        if (SV == 0) process_tile<M, true, false, BASE_NONE, false, false, TOP>(P, TR, S, a, false, &D, lw);
-        else if (SV == 1) process_tile<M, false, true, BASE_NONE, true, false, TOP>(P, TR, S, a, false, &D, lw);
-        else process_tile<M, false, true, BASE_Y, true, true, TOP>(P, TR, S, a, first, &D, lw);
+        if (SV == 0) process_tile<M, true, false, BASE_NONE, false, false, TOP>(P, D, TR, S, a, false, true, lw);
+        else if (SV == 1) process_tile<M, false, true, BASE_NONE, true, false, TOP>(P, D, TR, S, a, false, true, lw);
+        else process_tile<M, false, true, BASE_Y, true, true, TOP>(P, D, TR, S, a, first, true, lw);
     }
 }
 

@@ -100,6 +100,22 @@ HEOM_HD uint32_t live_slots(int kind, bool chi, uint64_t vq, uint64_t vr, int M)
 }
 static_assert(sizeof(TileRec) == 32, "TileRec layout");
 
+// Per-variable decode record, relative to the variable's tile:
+//   x = p | A << 7 | B << 12 | isT << 17 | goff << 18
+//   y = live hierarchy slots (bit j, slot order as in live_slots)
+// p: pattern index within the tile (< VREC_MAX_NP; every block has at least
+// four variables, so a 512-variable tile holds at most 128 patterns); A, B:
+// row and column category + 1 (0 = cavity); isT: the variable is T_{A-1};
+// goff: position of its first gather index in the tile's list.
+struct VarRec {
+    uint32_t x, y;
+};
+static_assert(sizeof(VarRec) == 8, "VarRec layout");
+constexpr uint32_t VREC_MAX_NP = 128u, VREC_MAX_GOFF = 16383u;
+HEOM_HD VarRec vrec_pack(uint32_t p, uint32_t A, uint32_t B, bool isT, uint32_t goff, uint32_t live) {
+    return VarRec{p | (A << 7) | (B << 12) | ((uint32_t)isT << 17) | (goff << 18), live};
+}
+
 // Per-instance numeric parameters (device image header). 256-byte aligned.
 struct InstParams {
     double g;          // single-molecule coupling
@@ -116,7 +132,7 @@ struct InstParams {
     int32_t m, L, d, n_pat;
     uint32_t n_var, n_tiles, tile_vars, max_np, max_nc, max_ng, lds_bytes, pad;
     // byte offsets of the sections from the image base
-    uint64_t off_lut, off_hdr, off_cat, off_gidx, off_tile;
+    uint64_t off_lut, off_hdr, off_cat, off_gidx, off_tile, off_vrec;
 };
 
 struct HostTables {
@@ -134,6 +150,7 @@ struct HostTables {
     std::vector<uint32_t> conn_target;  // target pattern index per Conn
     std::vector<TileRec> tiles;         // workgroup tiles
     std::vector<uint32_t> gidx;         // per-tile lists of gather target indices
+    std::vector<VarRec> vrec;           // per-variable decode records
     uint32_t max_np = 0, max_nc = 0, max_ng = 0, lds_bytes = 0;
     std::vector<uint16_t> pat_ids;      // flat: d dist ids + pool ids
     std::vector<uint32_t> pat_start;    // per pattern start in pat_ids, then end

@@ -467,6 +467,38 @@ void expand_gathers(const HostTables &t, uint32_t p, std::vector<uint32_t> *out)
     }
 }
 
+// Decode records of the variables of one tile, in variable order (VarRec).
+static int var_records(const HostTables &t, const TileRec &r, std::vector<VarRec> *out) {
+    const int M = t.m;
+    uint32_t goff = 0;
+    for (uint32_t pi = 0; pi < r.np; ++pi) {
+        const PatHdr &H = t.hdr[r.p0 + pi];
+        const int G = H.G, G1 = G + 1;
+        const bool chi = H.tier < t.L;
+        const CatRec *cats = &t.cat[H.cat_base];
+        for (uint32_t loc = 0; loc < H.size; ++loc) {
+            int A, B;
+            bool isT = false;
+            if (loc < (uint32_t)(G1 * G1)) {
+                A = (int)loc / G1;
+                B = (int)loc - A * G1;
+            } else {
+                uint32_t mask = H.tmask;
+                for (int s = (int)loc - G1 * G1; s > 0; --s) mask &= mask - 1u;
+                A = B = __builtin_ffs(mask);
+                isT = true;
+            }
+            const int kind = (A == 0 && B == 0) ? KIND_Z : (B == 0 ? KIND_X : (A == 0 ? KIND_Y : ((A == B && !isT) ? KIND_P : KIND_S)));
+            const CatRec cq = A > 0 ? cats[A - 1] : CatRec{}, cr = B > 0 ? cats[B - 1] : CatRec{};
+            const uint32_t live = live_slots(kind, chi, cq.vec, cr.vec, M);
+            if (goff > VREC_MAX_GOFF) return HEOM_E_UNSUPPORTED;
+            out->push_back(vrec_pack(pi, (uint32_t)A, (uint32_t)B, isT, goff, live));
+            goff += (uint32_t)__builtin_popcount(live);
+        }
+    }
+    return goff == r.ng ? HEOM_OK : HEOM_E_INVAL;
+}
+
 int make_tiles(HostTables *t, int tile_vars, std::string *err) {
     uint32_t maxblk = 0;
     for (auto &h : t->hdr) maxblk = std::max(maxblk, h.size);
@@ -484,6 +516,8 @@ int make_tiles(HostTables *t, int tile_vars, std::string *err) {
     size_t i = 0;
     t->max_np = t->max_nc = t->max_ng = 0;
     t->gidx.clear();
+    t->vrec.clear();
+    t->vrec.reserve(t->n_var);
     while (i < np) {
         TileRec r{};
         r.p0 = (uint32_t)i;
@@ -498,6 +532,11 @@ int make_tiles(HostTables *t, int tile_vars, std::string *err) {
         for (uint32_t p = r.p0; p < r.p0 + r.np; ++p) expand_gathers(*t, p, &t->gidx);
         if (t->gidx.size() > 0xffffffffull) { *err = "more than 2^32-1 hierarchy gathers"; return HEOM_E_TOO_LARGE; }
         r.ng = (uint32_t)t->gidx.size() - r.g0;
+        if (r.np > VREC_MAX_NP || r.ng > VREC_MAX_GOFF + 1u) {
+            *err = "a tile has more patterns or hierarchy gathers than its records can address";
+            return HEOM_E_UNSUPPORTED;
+        }
+        if (int rc = var_records(*t, r, &t->vrec)) { *err = "variable records do not match the gather lists"; return rc; }
         // each tile's list starts on a 16-byte boundary (staged as 16-byte words)
         while (t->gidx.size() % 4) t->gidx.push_back(0u);
         t->max_np = std::max(t->max_np, r.np);
@@ -508,8 +547,9 @@ int make_tiles(HostTables *t, int tile_vars, std::string *err) {
     t->top_tile = (uint32_t)t->tiles.size();
     for (size_t k = 0; k < t->tiles.size(); ++k)
         if (t->hdr[t->tiles[k].p0].tier == t->L) { t->top_tile = (uint32_t)k; break; }
-    // LDS per workgroup: values, pattern headers, categories, connections
-    t->lds_bytes = 16u * tile_vars + 32u * t->max_np + 16u * t->max_nc + 4u * ((t->max_ng + 3u) & ~3u) +
+    // LDS per workgroup: values, grouped sums, pattern headers, categories,
+    // gather indices, coefficient tables
+    t->lds_bytes = 32u * tile_vars + 32u * t->max_np + 16u * t->max_nc + 4u * ((t->max_ng + 3u) & ~3u) +
                    16u * (uint32_t)t->m * (uint32_t)(t->L + 1);
     if (t->lds_bytes > 64u * 1024u) {
         *err = "tile needs more than 64 KiB of LDS";
@@ -576,13 +616,14 @@ static InstParams make_params(const HostTables &num, const HostTables &st) {
     ip.off_hdr = o;   o = align256(o + st.hdr.size() * sizeof(PatHdr));
     ip.off_cat = o;   o = align256(o + st.cat.size() * sizeof(CatRec));
     ip.off_gidx = o;  o = align256(o + st.gidx.size() * sizeof(uint32_t));
-    ip.off_tile = o;
+    ip.off_tile = o;  o = align256(o + st.tiles.size() * sizeof(TileRec));
+    ip.off_vrec = o;
     return ip;
 }
 
 size_t image_bytes(const HostTables &t) {
     const InstParams ip = make_params(t, t);
-    return align256(ip.off_tile + t.tiles.size() * sizeof(TileRec));
+    return align256(ip.off_vrec + t.vrec.size() * sizeof(VarRec));
 }
 
 int pack_params(const HostTables &t, const heom_problem *p, std::vector<unsigned char> *out, std::string *err) {
@@ -617,6 +658,7 @@ void pack_image(HostTables *t) {
     std::memcpy(t->image.data() + ip.off_cat, t->cat.data(), t->cat.size() * sizeof(CatRec));
     std::memcpy(t->image.data() + ip.off_gidx, t->gidx.data(), t->gidx.size() * sizeof(uint32_t));
     std::memcpy(t->image.data() + ip.off_tile, t->tiles.data(), t->tiles.size() * sizeof(TileRec));
+    std::memcpy(t->image.data() + ip.off_vrec, t->vrec.data(), t->vrec.size() * sizeof(VarRec));
 }
 
 }  // namespace heom
