@@ -132,6 +132,27 @@ int heom_upload(heom_tables *t, void *dev, size_t bytes, void *stream);
 int heom_tier0_pure(const heom_tables *t, const double a_c[2], const double *a_dist,
                     const double a_pool[2], double *out);
 
+/* Tier-0 unique variables of any operator A on the single-excitation space
+ * that is invariant under relabelings of the pool molecules (Hermitian or
+ * not, e.g. the representative operators |e_1><c|, |e_1><e_2| of the
+ * linear reconstruction of Sec. VII.A, Table II). A is given by its
+ * entries between representative basis states, R[a][b] = <a|A|b>, on the
+ * d+3 slots 0 = cavity, 1..d = distinguished molecules e_1..e_d, d+1 = a
+ * pool molecule, d+2 = a second pool molecule: R is (d+3)x(d+3) complex,
+ * row-major (re, im) pairs, host. Read are the entries among slots
+ * 0..d+1 and R[d+1][d+2] (the coherence between two different pool
+ * molecules); the others follow from pool invariance and are ignored.
+ * out: 2*tier0_size doubles (host). */
+int heom_tier0_operator(const heom_tables *t, const double *R, double *out);
+
+/* Inverse of heom_tier0_operator: the (d+3)x(d+3) slot matrix R (host,
+ * every entry written; entries of slot d+2 mirror slot d+1 except the
+ * pool-pool coherence) of the operator whose tier-0 block is `tier0`
+ * (2*tier0_size doubles, host), e.g. rho_S(t) read back from a propagated
+ * state. Entries of absent slots (a pool with fewer than two molecules)
+ * are 0. */
+int heom_tier0_expand(const heom_tables *t, const double *tier0, double *R);
+
 /* Factorized initial condition (Eqs. factorized-initial-zero/-higher):
  * y_dev (n_var complex128) gets the tier-0 variables `tier0` (host,
  * 2*tier0_size doubles) and zeros elsewhere. Requires heom_upload. */

@@ -910,6 +910,63 @@ int heom_tier0_pure(const heom_tables *h, const double a_c[2], const double *a_d
     return HEOM_OK;
 }
 
+// Representative slot of tier-0 index idx (0 = cavity, q+1 = category q):
+// distinguished molecules come first among the empty pattern's categories,
+// in label order, then the pool.
+static int tier0_slot(const HostTables &t, int idx) {
+    if (idx == 0) return 0;
+    const CatRec &c = t.cat[t.hdr[0].cat_base + idx - 1];
+    return (c.flags & CAT_DIST) ? idx : t.d + 1;
+}
+
+int heom_tier0_operator(const heom_tables *h, const double *R, double *out) {
+    if (!h || !R || !out) return fail(HEOM_E_INVAL, "NULL argument");
+    const HostTables &t = h->t;
+    const PatHdr &H = t.hdr[0];
+    const int G = H.G, G1 = G + 1, ns = t.d + 3;
+    auto put = [&](size_t pos, int a, int b) {
+        out[2 * pos] = R[2 * (a * ns + b)];
+        out[2 * pos + 1] = R[2 * (a * ns + b) + 1];
+    };
+    for (int A = 0; A < G1; ++A)
+        for (int B = 0; B < G1; ++B) put((size_t)A * G1 + B, tier0_slot(t, A), tier0_slot(t, B));
+    size_t pos = (size_t)G1 * G1;
+    for (int q = 0; q < G; ++q)
+        if ((H.tmask >> q) & 1u) put(pos++, t.d + 1, t.d + 2);   // two different pool molecules
+    return HEOM_OK;
+}
+
+int heom_tier0_expand(const heom_tables *h, const double *tier0, double *R) {
+    if (!h || !tier0 || !R) return fail(HEOM_E_INVAL, "NULL argument");
+    const HostTables &t = h->t;
+    const PatHdr &H = t.hdr[0];
+    const int G = H.G, G1 = G + 1, ns = t.d + 3;
+    std::fill(R, R + 2 * ns * ns, 0.0);
+    auto get = [&](size_t pos, int a, int b) {
+        R[2 * (a * ns + b)] = tier0[2 * pos];
+        R[2 * (a * ns + b) + 1] = tier0[2 * pos + 1];
+    };
+    const int pa = t.d + 1, pb = t.d + 2;
+    for (int A = 0; A < G1; ++A)
+        for (int B = 0; B < G1; ++B) {
+            const int a = tier0_slot(t, A), b = tier0_slot(t, B);
+            get((size_t)A * G1 + B, a, b);
+            // the second pool molecule has the same entries as the first
+            // (the coherence between the two is the T variable, below)
+            if (a == pa && b != pa) get((size_t)A * G1 + B, pb, b);
+            if (b == pa && a != pa) get((size_t)A * G1 + B, a, pb);
+            if (a == pa && b == pa) get((size_t)A * G1 + B, pb, pb);
+        }
+    size_t pos = (size_t)G1 * G1;
+    for (int q = 0; q < G; ++q)
+        if ((H.tmask >> q) & 1u) {
+            get(pos, pa, pb);
+            get(pos, pb, pa);
+            ++pos;
+        }
+    return HEOM_OK;
+}
+
 int heom_init_state(const heom_tables *h, const double *tier0, void *y_dev, void *stream) {
     if (int rc = check_ready(h)) return rc;
     if (!tier0) return fail(HEOM_E_INVAL, "tier0 is NULL");

@@ -26,6 +26,7 @@ ERRORS = {-1: "E_INVAL", -2: "E_NOMEM", -3: "E_TOO_LARGE", -4: "E_HIP", -5: "E_N
 
 # every symbol include/heom.h declares
 SYMBOLS = ["heom_build_tables", "heom_set_params", "heom_table_info", "heom_upload", "heom_tier0_pure",
+           "heom_tier0_operator", "heom_tier0_expand",
            "heom_init_state", "heom_rhs", "heom_propagate", "heom_observables", "heom_export_layout",
            "heom_export_coefficients", "heom_free_tables", "heom_last_error", "heom_version",
            "heom_set_tuning", "heom_get_tuning", "heom_work_status", "heom_params_bytes",
@@ -79,6 +80,8 @@ def _load():
         "heom_table_info": [vp, ctypes.POINTER(_Sizes)],
         "heom_upload": [vp, vp, ctypes.c_size_t, vp],
         "heom_tier0_pure": [vp, dp, dp, dp, dp],
+        "heom_tier0_operator": [vp, dp, dp],
+        "heom_tier0_expand": [vp, dp, dp],
         "heom_init_state": [vp, dp, vp, vp],
         "heom_rhs": [vp, vp, vp, vp],
         "heom_propagate": [vp, vp, vp, ctypes.c_size_t, ctypes.c_double, i64, i64, vp, ctypes.c_int, vp],
@@ -199,6 +202,30 @@ class Tables:
         ad = _dbl([x for z in a_dist for x in (complex(z).real, complex(z).imag)]) if len(a_dist) else None
         _check(LIB.heom_tier0_pure(self._h, ac, ad, ap, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
         return out.view(np.complex128)
+
+    def tier0_operator(self, R: np.ndarray) -> np.ndarray:
+        """Tier-0 block of a pool-invariant operator given by its
+        (d+3)x(d+3) slot matrix R (cavity, distinguished molecules, two pool
+        molecules)."""
+        ns = self.problem.d + 3
+        R = np.ascontiguousarray(np.asarray(R, dtype=np.complex128))
+        if R.shape != (ns, ns):
+            raise ValueError(f"R must be {ns}x{ns}")
+        n0 = self.info()["tier0_size"]
+        out = np.zeros(2 * n0)
+        Rv = R.view(np.float64)
+        _check(LIB.heom_tier0_operator(self._h, Rv.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                       out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        return out.view(np.complex128)
+
+    def tier0_expand(self, tier0: np.ndarray) -> np.ndarray:
+        """Slot matrix R of the operator whose tier-0 block is `tier0`."""
+        ns = self.problem.d + 3
+        t0 = np.ascontiguousarray(np.asarray(tier0, dtype=np.complex128)).view(np.float64)
+        R = np.zeros((ns, ns), dtype=np.complex128)
+        _check(LIB.heom_tier0_expand(self._h, t0.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                     R.view(np.float64).ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        return R
 
     def init_state(self, tier0: np.ndarray, y, stream=None):
         t0 = np.ascontiguousarray(np.asarray(tier0, dtype=np.complex128)).view(np.float64)

@@ -107,6 +107,33 @@ def config_roofline_probe() -> Problem:
                    eps=0.0, omega_c=0.0, g=0.005, kappa=0.01)
 
 
+CM_TO_RAD_PER_FS = 2.0 * math.pi * 2.99792458e-5   # E[cm^-1] -> omega[rad/fs]
+
+
+def config_paper_shape(N: int, d: int = 0) -> Problem:
+    """The paper's single-exponential runs (Sec. VIII), in rad/fs and fs:
+    omega_cav = eps = 10000 cm^-1, collective Rabi splitting 500 cm^-1 held
+    fixed with g = Omega_R / (2 sqrt N) (Eq. g-fixed-Rabi), Drude-Lorentz
+    bath lam = 50 cm^-1, gam = 18 cm^-1, kT = 208 cm^-1 (300 K), one
+    exponential (the exact Debye term c = lam gam (cot(gam/2kT) - i),
+    nu = gam) and the Ishizaki-Tanimura terminator for the omitted
+    Matsubara terms, Delta = sum_k c_k/nu_k = 2 lam kT/gam - lam cot(gam/2kT);
+    L = 25, no loss. The time step is 0.5 fs (PAPER_SHAPE_DT). d = 0 for
+    symmetric starts (upper polariton), d = 1 for the localized and
+    cavity-site superposition starts."""
+    f = CM_TO_RAD_PER_FS
+    lam, gam, kT = 50.0 * f, 18.0 * f, 208.0 * f
+    c = complex(lam * gam / math.tan(gam / (2.0 * kT)), -lam * gam)
+    delta = 2.0 * lam * kT / gam - lam / math.tan(gam / (2.0 * kT))
+    omega_r = 500.0 * f
+    return Problem(N=N, m=1, L=25, d=d, c=[c], c_check=[c.conjugate()], nu=[gam],
+                   eps=10000.0 * f, omega_c=10000.0 * f, g=omega_r / (2.0 * math.sqrt(N)),
+                   kappa=0.0, terminator=delta)
+
+
+PAPER_SHAPE_DT = 0.5
+
+
 def _matsubara_pole_too_close(gam: float, m: int, kT: float) -> bool:
     for k in range(1, m):
         vk = 2.0 * math.pi * k * kT

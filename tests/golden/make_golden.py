@@ -9,6 +9,10 @@ the oracle's unique-variable generator, observables of the tier-0 block every
 Workloads:
   localized -- N=64, m=2, L=6, d=1, rho(0)=|e_1><e_1|, dt=0.02, 10000 steps
   saturated -- N=10^4, m=3, L=8, rho(0)=|+><+|, dt=0.02, 10000 steps
+  paper_n5_up -- the paper's L=25 single-exponential workload (Sec. VIII,
+      rad/fs units) at N=5, upper-polariton start, dt=0.5 fs, 400 steps
+  paper_n3_superposition -- the same at N=3 with one distinguished molecule,
+      rho(0) from sqrt(0.3)|e_1> + sqrt(0.7)|c>, dt=0.5 fs, 400 steps
 """
 import json
 import math
@@ -28,6 +32,10 @@ from paper_2608_20657_amd import workloads as W  # noqa: E402
 RUNS = {
     "localized": dict(dt=0.02, steps=10000, every=100, state="site1"),
     "saturated": dict(dt=0.02, steps=10000, every=100, state="upper_polariton"),
+    "paper_n5_up": dict(dt=W.PAPER_SHAPE_DT, steps=400, every=20, state="upper_polariton",
+                        problem=lambda: W.config_paper_shape(5, 0)),
+    "paper_n3_superposition": dict(dt=W.PAPER_SHAPE_DT, steps=400, every=20, state="site1_cavity",
+                                   problem=lambda: W.config_paper_shape(3, 1)),
 }
 
 
@@ -36,6 +44,8 @@ def amplitude(p, state):
         return lambda i: 1.0 if i == 1 else 0.0
     if state == "photon":
         return lambda i: 1.0 if i == 0 else 0.0
+    if state == "site1_cavity":
+        return lambda i: math.sqrt(0.7) if i == 0 else (math.sqrt(0.3) if i == 1 else 0.0)
     if state == "upper_polariton":
         th = observables.theta(p.N, p.eps, p.omega_c, p.g)
         return lambda i: math.cos(th) if i == 0 else math.sin(th) / math.sqrt(p.N)
@@ -44,7 +54,7 @@ def amplitude(p, state):
 
 def make(name):
     run = RUNS[name]
-    p = W.WORKLOADS[name]()
+    p = run["problem"]() if "problem" in run else W.WORKLOADS[name]()
     t0 = time.time()
     S = uvar.UVarSystem(p)
     A = S.generator()

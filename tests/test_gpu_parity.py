@@ -84,6 +84,26 @@ def test_rhs_largest_structure_sampled():
         assert abs(got[i] - want) <= 1e-13 * scale + 1e-300, i
 
 
+@pytest.mark.parametrize("d", [0, 1])
+def test_rhs_paper_shape_sampled(d):
+    """The paper's L=25 workload at N=10^12 (saturated: 306,751 or
+    1,715,600 unique variables), rows sampled against the oracle."""
+    p = W.config_paper_shape(10 ** 12, d)
+    T, torch = upload(p)
+    n = T.info()["n_var"]
+    y = W.random_vector(n, 11 + d)
+    got = gpu_rhs(T, torch, y)
+    S = uvar.UVarSystem(p)
+    assert S.n_var == n
+    rng = np.random.default_rng(13 + d)
+    rows = rng.choice(n, 300, replace=False).tolist() + [0, 1, n - 1] + [b.offset for b in S.blocks[-2:]]
+    ref = S.rows_at(rows)
+    for i in rows:
+        want = sum(c * y[j] for j, c in ref[i].items())
+        scale = sum(abs(c) * abs(y[j]) for j, c in ref[i].items())
+        assert abs(got[i] - want) <= 1e-13 * scale + 1e-300, i
+
+
 def test_rhs_deterministic():
     p = W.config_localized()
     T, torch = upload(p)
@@ -158,24 +178,42 @@ def _golden(name):
     return json.load(open(path))
 
 
-@pytest.mark.parametrize("name", ["localized", "saturated"])
+PAPER_RUNS = {"paper_n5_up": (5, 0), "paper_n3_superposition": (3, 1)}
+
+
+def _problem_and_tier0(name, T_of, state):
+    """Problem of a golden run and its tier-0 block on tables T_of(p)."""
+    if name in PAPER_RUNS:
+        p = W.config_paper_shape(*PAPER_RUNS[name])
+    else:
+        p = W.WORKLOADS[name]()
+    T, torch = T_of(p)
+    if state == "site1_cavity":            # sqrt(0.3)|e_1> + sqrt(0.7)|c>
+        t0 = T.tier0_pure(math.sqrt(0.7), 0.0, [math.sqrt(0.3)])
+    else:
+        t0 = named_tier0(T, p, state)
+    return p, T, torch, t0
+
+
+GOLDEN_RUNS = ["localized", "saturated", "paper_n5_up", "paper_n3_superposition"]
+
+
+@pytest.mark.parametrize("name", GOLDEN_RUNS)
 def test_propagate_fp64_vs_golden(name):
     g = _golden(name)
-    p = W.WORKLOADS[name]()
-    T, torch = upload(p)
-    _, obs = gpu_propagate(T, torch, named_tier0(T, p, g["state"]), g["dt"], g["steps"], g["every"])
+    p, T, torch, t0 = _problem_and_tier0(name, upload, g["state"])
+    _, obs = gpu_propagate(T, torch, t0, g["dt"], g["steps"], g["every"])
     ref = np.array(g["observables"])
     assert obs.shape == ref.shape
     for j in range(9):
         assert np.abs(obs[:, j] - ref[:, j]).max() <= 1e-10 * max(np.abs(ref[:, j]).max(), 1e-300), j
 
 
-@pytest.mark.parametrize("name", ["localized", "saturated"])
+@pytest.mark.parametrize("name", GOLDEN_RUNS)
 def test_propagate_fp32_vs_golden(name):
     g = _golden(name)
-    p = W.WORKLOADS[name]()
-    T, torch = upload(p)
-    _, obs = gpu_propagate(T, torch, named_tier0(T, p, g["state"]), g["dt"], g["steps"], g["every"], precision=1)
+    p, T, torch, t0 = _problem_and_tier0(name, upload, g["state"])
+    _, obs = gpu_propagate(T, torch, t0, g["dt"], g["steps"], g["every"], precision=1)
     ref = np.array(g["observables"])
     err = np.abs(obs[:, 1:9] - ref[:, 1:9]).max()
     assert err <= 1e-5, err

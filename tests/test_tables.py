@@ -138,3 +138,18 @@ def test_too_many_categories_rejected():
     with pytest.raises(heom.HeomError) as e:
         heom.Tables(p)
     assert e.value.code == -6
+
+
+@pytest.mark.parametrize("N,d,patterns,unique", [
+    (10 ** 12, 0, 9296, 306751),     # symmetric start, saturated (Sec. VII.C)
+    (10 ** 12, 1, 41391, 1715600),   # one distinguished molecule, saturated
+    (25, 0, 9296, 306743),
+    (26, 0, 9296, 306750),
+])
+def test_paper_shape_table_sizes(N, d, patterns, unique):
+    """The library's tables for the paper's L=25 single-exponential workload
+    have the pattern and unique-variable counts the paper prints."""
+    from paper_2608_20657_amd import heom
+    info = heom.Tables(W.config_paper_shape(N, d)).info()
+    assert info["n_patterns"] == patterns
+    assert info["n_var"] == unique
