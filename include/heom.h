@@ -304,6 +304,29 @@ int heom_batch_commit(heom_batch *b, void *dev, size_t bytes, void *stream);
  * in heom_propagate. Errors: E_STATE if not committed since the last change. */
 int heom_batch_propagate(heom_batch *b, int64_t nsteps, int precision, void *stream);
 
+/* Replay whole groups of `steps` RK4 steps from a HIP graph captured on the
+ * stream of heom_batch_propagate (0, the default, launches every kernel
+ * directly; at most 4096). Small problems are bound by the host's launch
+ * rate, which a replayed graph avoids. The graph is captured at the first
+ * heom_batch_propagate with at least `steps` steps after a commit (or a
+ * change of precision or of this setting) and replayed for as many whole
+ * groups as fit; the remaining steps are launched directly. The step
+ * index that selects observable rows is kept on the device, so replays and
+ * direct launches give bitwise the same results. Not used on the null
+ * stream, which cannot be captured. */
+int heom_batch_set_graph(heom_batch *b, int32_t steps);
+
+/* Launch shape: the batch's tiles fall into groups of one m, tile size and
+ * tier class. The smallest groups with m <= 4, up to max_tiles tiles in
+ * all, are run as one launch per RK4 stage (each workgroup picks the kernel
+ * variant of its slot's m and tier class); every other group has its own
+ * launch. Small problems are bound by the latency of dependent launches,
+ * which the merged launch avoids; large groups keep their own kernels, whose
+ * register use allows more waves. 0 = one launch per group. Default 16384.
+ * Results are bitwise the same either way. Takes effect at the next
+ * heom_batch_commit (required). */
+int heom_batch_set_merge(heom_batch *b, int32_t max_tiles);
+
 /* Steps a slot has taken since it was set. */
 int heom_batch_slot_steps(const heom_batch *b, int32_t slot, int64_t *steps);
 

@@ -43,11 +43,22 @@ struct heom_batch {
     // One launch per group: tiles of one m, one tile size and one tier class
     // (top-tier tiles have no up moves and run a lighter kernel variant).
     struct Group {
-        int m;
+        int m;       // 0: every tile of the batch in one launch (batch_stage_merged)
         bool top;
         uint32_t block, lds, first, count;
     };
     std::vector<Group> groups;
+    // Steps replayed from a captured HIP graph (0 = launch every kernel).
+    int32_t graph_steps = 0;
+    // The smallest groups with m <= 4, up to this many tiles in all, run each
+    // stage as one launch instead of one per group.
+    int32_t merge_tiles = 16384;
+    hipGraphExec_t gexec = nullptr;
+    int gprec = -1;
+    size_t ctr_off = 0;                 // device step counter in the batch buffer
+    ~heom_batch() {
+        if (gexec) (void)hipGraphExecDestroy(gexec);
+    }
 };
 
 namespace {
@@ -582,8 +593,9 @@ struct SlotRec {
     double dt;
 };
 struct BatchTile {
-    uint32_t slot, tile;
+    uint32_t slot, tile;   // tile | BTILE_TOP for a tile of the top tier
 };
+constexpr uint32_t BTILE_TOP = 0x80000000u;
 
 // A pointer read from memory has no known address space, so accesses
 // through it would be flat instructions (which also hold up every LDS wait)
@@ -600,12 +612,21 @@ __device__ __forceinline__ T *as_global(T *p) {
 // SV selects the stage's vector pattern at compile time (FP64: 0 = first
 // stage, 1 = the others; FP32: 0 = first, 1 = second and third, 2 = last),
 // so each instance holds only the registers of its own pattern.
-template <int M, int PREC, bool TOP, int SV>
-__global__ __launch_bounds__(MAX_TILE) void batch_stage_kernel(const SlotRec *slots, const BatchTile *btiles, int s,
-                                                             int64_t steps_done, int64_t st, uint32_t policy) {
-    extern __shared__ __align__(16) unsigned char smem[];
-    const BatchTile B = btiles[blockIdx.x];
-    SlotRec R = slots[B.slot];
+// Everything a workgroup of a batch launch needs about its tile's slot.
+struct BatchCtx {
+    SlotRec R;
+    Dev D;
+    TileRec TR;
+    StageArgs a;
+    bool first;
+};
+
+template <int PREC>
+__device__ __forceinline__ BatchCtx batch_ctx(const SlotRec *slots, uint32_t slot, uint32_t tile, int s,
+                                              const int64_t *ctr, uint32_t policy) {
+    BatchCtx c;
+    SlotRec &R = c.R;
+    R = slots[slot];
     R.img = as_global(R.img);
     R.params = as_global(R.params);
     R.y = as_global(R.y);
@@ -616,7 +637,7 @@ __global__ __launch_bounds__(MAX_TILE) void batch_stage_kernel(const SlotRec *sl
     R.u3 = as_global(R.u3);
     R.obs = as_global(R.obs);
     const InstParams &P = *reinterpret_cast<const InstParams *>(R.params);
-    Dev D;
+    Dev &D = c.D;
     D.ip = &P;
     D.lut = reinterpret_cast<const double *>(R.params + P.off_lut);
     D.hdr = reinterpret_cast<const PatHdr *>(R.img + P.off_hdr);
@@ -624,23 +645,23 @@ __global__ __launch_bounds__(MAX_TILE) void batch_stage_kernel(const SlotRec *sl
     D.gidx = reinterpret_cast<const uint32_t *>(R.img + P.off_gidx);
     D.tiles = reinterpret_cast<const TileRec *>(R.img + P.off_tile);
     D.vrec = reinterpret_cast<const VarRec *>(R.img + P.off_vrec);
-    const Smem S = carve(smem, P);
-    const TileRec TR = D.tiles[B.tile];
-    const uint32_t lw = lut_words(P);
+    c.TR = D.tiles[tile];
     const double h = R.dt;
-    const int64_t gst = R.step0 + steps_done + st;   // steps of this slot so far, this one included
-    StageArgs a{};
+    // steps of this slot so far, this one included; the counter (steps of the
+    // batch since the last commit) is advanced on the device, so a captured
+    // graph of steps replays with the right observable rows
+    const int64_t gst = R.step0 + *as_global(ctr) + 1;
+    StageArgs &a = c.a;
+    a = StageArgs{};
     a.policy = policy;
     a.alpha = s == 0 ? h / 4.0 : (s == 1 ? h / 3.0 : (s == 2 ? h / 2.0 : h));
     a.obs = (s == 3 && R.obs != nullptr && R.obs_every > 0 && gst % R.obs_every == 0 && gst / R.obs_every < R.obs_cap)
                 ? R.obs + (gst / R.obs_every) * HEOM_NOBS : nullptr;
-    const bool first = B.tile == 0;
+    c.first = tile == 0;
     if (PREC == HEOM_FP64) {
         a.in64 = s == 0 ? R.y : (s == 2 ? R.w1 : R.w0);
         a.ybase = R.y;
         a.out64 = s == 3 ? R.y : (s == 1 ? R.w1 : R.w0);
-        if (SV == 0) process_tile<M, true, false, BASE_IN, false, true, TOP>(P, D, TR, S, a, first, true, lw);
-        else process_tile<M, true, false, BASE_Y, false, true, TOP>(P, D, TR, S, a, first, true, lw);
     } else {
         a.in64 = R.y;
         a.in32 = s == 1 ? R.u1 : (s == 2 ? R.u2 : R.u3);
@@ -649,9 +670,64 @@ __global__ __launch_bounds__(MAX_TILE) void batch_stage_kernel(const SlotRec *sl
         a.ybase = R.y;
         a.out32 = s == 0 ? R.u1 : (s == 1 ? R.u2 : R.u3);
         a.out64 = R.y;
-        if (SV == 0) process_tile<M, true, false, BASE_NONE, false, false, TOP>(P, D, TR, S, a, false, true, lw);
-        else if (SV == 1) process_tile<M, false, true, BASE_NONE, true, false, TOP>(P, D, TR, S, a, false, true, lw);
-        else process_tile<M, false, true, BASE_Y, true, true, TOP>(P, D, TR, S, a, first, true, lw);
+    }
+    return c;
+}
+
+// The stage pattern SV of one tile (FP64: 0 = first stage, 1 = the others;
+// FP32: 0 = first, 1 = second and third, 2 = last).
+template <int M, int PREC, bool TOP, int SV>
+__device__ __forceinline__ void batch_tile(const BatchCtx &c, unsigned char *smem) {
+    const InstParams &P = *c.D.ip;
+    const Smem S = carve(smem, P);
+    const uint32_t lw = lut_words(P);
+    if (PREC == HEOM_FP64) {
+        if (SV == 0) process_tile<M, true, false, BASE_IN, false, true, TOP>(P, c.D, c.TR, S, c.a, c.first, true, lw);
+        else process_tile<M, true, false, BASE_Y, false, true, TOP>(P, c.D, c.TR, S, c.a, c.first, true, lw);
+    } else {
+        if (SV == 0) process_tile<M, true, false, BASE_NONE, false, false, TOP>(P, c.D, c.TR, S, c.a, false, true, lw);
+        else if (SV == 1) process_tile<M, false, true, BASE_NONE, true, false, TOP>(P, c.D, c.TR, S, c.a, false, true, lw);
+        else process_tile<M, false, true, BASE_Y, true, true, TOP>(P, c.D, c.TR, S, c.a, c.first, true, lw);
+    }
+}
+
+// One RK4 stage of every tile of every slot in a tile list (all of one m,
+// one tile size and one tier class). Each variable is computed by the same
+// arithmetic as in stage_kernel, so a problem's trajectory does not depend
+// on the other problems in the batch. SV is a template parameter, so each
+// instance holds only the registers of its own stage pattern.
+template <int M, int PREC, bool TOP, int SV>
+__global__ __launch_bounds__(MAX_TILE) void batch_stage_kernel(const SlotRec *slots, const BatchTile *btiles, int s,
+                                                             const int64_t *ctr, uint32_t policy) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const BatchTile B = btiles[blockIdx.x];
+    const BatchCtx c = batch_ctx<PREC>(slots, B.slot, B.tile & ~BTILE_TOP, s, ctr, policy);
+    batch_tile<M, PREC, TOP, SV>(c, smem);
+}
+
+// The same for a whole batch in one launch per stage, for batches of small
+// problems whose stages are bound by launch latency: each workgroup takes the
+// kernel variant of its slot's m (at most MERGE_MAX_M) and tier class. The
+// block has the largest tile size of the batch (threads past a tile's last
+// variable only help stage its metadata).
+constexpr int MERGE_MAX_M = 4;
+template <int PREC, int SV>
+__global__ __launch_bounds__(MAX_TILE) void batch_stage_merged(const SlotRec *slots, const BatchTile *btiles, int s,
+                                                             const int64_t *ctr, uint32_t policy) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const BatchTile B = btiles[blockIdx.x];
+    const bool top = (B.tile & BTILE_TOP) != 0;
+    const BatchCtx c = batch_ctx<PREC>(slots, B.slot, B.tile & ~BTILE_TOP, s, ctr, policy);
+    switch (c.D.ip->m * 2 + (top ? 1 : 0)) {
+        case 2: batch_tile<1, PREC, false, SV>(c, smem); break;
+        case 3: batch_tile<1, PREC, true, SV>(c, smem); break;
+        case 4: batch_tile<2, PREC, false, SV>(c, smem); break;
+        case 5: batch_tile<2, PREC, true, SV>(c, smem); break;
+        case 6: batch_tile<3, PREC, false, SV>(c, smem); break;
+        case 7: batch_tile<3, PREC, true, SV>(c, smem); break;
+        case 8: batch_tile<4, PREC, false, SV>(c, smem); break;
+        case 9: batch_tile<4, PREC, true, SV>(c, smem); break;
+        default: break;   // excluded when the batch is committed
     }
 }
 
@@ -766,32 +842,50 @@ int check_dev(const void *p, const char *name) {
 
 template <int M, int PREC, bool TOP>
 void batch_launch_group(const heom_batch::Group &g, hipStream_t s, const SlotRec *recs, const BatchTile *first,
-                        int stage, int64_t done, int64_t st, uint32_t policy) {
+                        int stage, const int64_t *ctr, uint32_t policy) {
     const dim3 grid(g.count), block(g.block);
     const int sv = stage == 0 ? 0 : (PREC == HEOM_FP64 ? 1 : (stage < 3 ? 1 : 2));
     if (sv == 0)
-        hipLaunchKernelGGL((batch_stage_kernel<M, PREC, TOP, 0>), grid, block, g.lds, s, recs, first, stage, done, st,
+        hipLaunchKernelGGL((batch_stage_kernel<M, PREC, TOP, 0>), grid, block, g.lds, s, recs, first, stage, ctr,
                            policy);
     else if (sv == 1)
-        hipLaunchKernelGGL((batch_stage_kernel<M, PREC, TOP, 1>), grid, block, g.lds, s, recs, first, stage, done, st,
+        hipLaunchKernelGGL((batch_stage_kernel<M, PREC, TOP, 1>), grid, block, g.lds, s, recs, first, stage, ctr,
                            policy);
     else if (PREC == HEOM_FP32)
-        hipLaunchKernelGGL((batch_stage_kernel<M, PREC, TOP, 2>), grid, block, g.lds, s, recs, first, stage, done, st,
+        hipLaunchKernelGGL((batch_stage_kernel<M, PREC, TOP, 2>), grid, block, g.lds, s, recs, first, stage, ctr,
                            policy);
 }
 
+// Advance the batch's device step counter by one (a single thread, after
+// the last stage of a step).
+__global__ void tick_kernel(int64_t *ctr) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) ctr[0] += 1;
+}
+
 template <int PREC>
-int batch_launch(const heom_batch *b, hipStream_t s, int stage, int64_t st, uint32_t policy) {
+int batch_launch(const heom_batch *b, hipStream_t s, int stage, uint32_t policy) {
     const SlotRec *recs = static_cast<const SlotRec *>(b->dev);
     const size_t tile_off = (sizeof(SlotRec) * b->slots.size() + 255) & ~(size_t)255;
     const BatchTile *tl = reinterpret_cast<const BatchTile *>(static_cast<const unsigned char *>(b->dev) + tile_off);
+    const int64_t *ctr = reinterpret_cast<const int64_t *>(static_cast<const unsigned char *>(b->dev) + b->ctr_off);
     for (const auto &g : b->groups) {
         const BatchTile *first = tl + g.first;
-        const int64_t done = b->steps_since_commit;
-#define HEOM_BCASE(MM)                                                                              \
-    case MM:                                                                                        \
-        if (g.top) batch_launch_group<MM, PREC, true>(g, s, recs, first, stage, done, st, policy);  \
-        else batch_launch_group<MM, PREC, false>(g, s, recs, first, stage, done, st, policy);       \
+        if (g.m == 0) {
+            const dim3 grid(g.count), block(g.block);
+            const int sv = stage == 0 ? 0 : (PREC == HEOM_FP64 ? 1 : (stage < 3 ? 1 : 2));
+            if (sv == 0)
+                hipLaunchKernelGGL((batch_stage_merged<PREC, 0>), grid, block, g.lds, s, recs, first, stage, ctr, policy);
+            else if (sv == 1)
+                hipLaunchKernelGGL((batch_stage_merged<PREC, 1>), grid, block, g.lds, s, recs, first, stage, ctr, policy);
+            else if (PREC == HEOM_FP32)
+                hipLaunchKernelGGL((batch_stage_merged<PREC, 2>), grid, block, g.lds, s, recs, first, stage, ctr, policy);
+            HIP_TRY(hipGetLastError());
+            continue;
+        }
+#define HEOM_BCASE(MM)                                                                         \
+    case MM:                                                                                   \
+        if (g.top) batch_launch_group<MM, PREC, true>(g, s, recs, first, stage, ctr, policy);  \
+        else batch_launch_group<MM, PREC, false>(g, s, recs, first, stage, ctr, policy);       \
         break;
         switch (g.m) {
             HEOM_BCASE(1) HEOM_BCASE(2) HEOM_BCASE(3) HEOM_BCASE(4)
@@ -801,6 +895,48 @@ int batch_launch(const heom_batch *b, hipStream_t s, int stage, int64_t st, uint
 #undef HEOM_BCASE
         HIP_TRY(hipGetLastError());
     }
+    return HEOM_OK;
+}
+
+// One RK4 step of every slot: four stage launches per group, then the tick.
+int batch_step(const heom_batch *b, hipStream_t s, int precision) {
+    const uint32_t policy = 6u;
+    for (int stage = 0; stage < 4; ++stage) {
+        const int rc = precision == HEOM_FP64 ? batch_launch<HEOM_FP64>(b, s, stage, policy)
+                                              : batch_launch<HEOM_FP32>(b, s, stage, policy);
+        if (rc) return rc;
+    }
+    int64_t *ctr = reinterpret_cast<int64_t *>(static_cast<unsigned char *>(b->dev) + b->ctr_off);
+    hipLaunchKernelGGL(tick_kernel, dim3(1), dim3(64), 0, s, ctr);
+    HIP_TRY(hipGetLastError());
+    return HEOM_OK;
+}
+
+// Capture graph_steps steps on stream s into b->gexec. The capture is ended
+// on every path, so the stream never stays in capture mode.
+int batch_capture(heom_batch *b, hipStream_t s, int precision) {
+    if (b->gexec) {
+        HIP_TRY(hipGraphExecDestroy(b->gexec));
+        b->gexec = nullptr;
+    }
+    HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed));
+    int rc = HEOM_OK;
+    for (int32_t k = 0; k < b->graph_steps && rc == HEOM_OK; ++k) rc = batch_step(b, s, precision);
+    const std::string launch_err = rc ? g_err : std::string();
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(s, &g);
+    if (rc) {
+        if (g) (void)hipGraphDestroy(g);
+        return fail(rc, launch_err);
+    }
+    if (e != hipSuccess) return fail(HEOM_E_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+    const hipError_t ei = hipGraphInstantiate(&b->gexec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (ei != hipSuccess) {
+        b->gexec = nullptr;
+        return fail(HEOM_E_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(ei));
+    }
+    b->gprec = precision;
     return HEOM_OK;
 }
 
@@ -1260,7 +1396,9 @@ int heom_batch_device_bytes(const heom_batch *b, size_t *bytes) {
     size_t nt = 0;
     for (const auto &S : b->slots)
         if (S.used) nt += S.tables->t.tiles.size();
-    *bytes = ((sizeof(SlotRec) * b->slots.size() + 255) & ~(size_t)255) + sizeof(BatchTile) * nt + 256;
+    // slot records, tile list, then the 8-byte step counter on its own 256 bytes
+    *bytes = ((sizeof(SlotRec) * b->slots.size() + 255) & ~(size_t)255) + ((sizeof(BatchTile) * nt + 255) & ~(size_t)255) +
+             256;
     return HEOM_OK;
 }
 
@@ -1298,18 +1436,23 @@ int heom_batch_commit(heom_batch *b, void *dev, size_t bytes, void *stream) {
         R.dt = S.dt;
     }
     // Group the tiles by (m, tile size, tier class); within a group, slot by
-    // slot in slot order and each slot's tiles in order.
+    // slot in slot order and each slot's tiles in order. Then the smallest
+    // groups with m <= MERGE_MAX_M, up to merge_tiles tiles in all, become one
+    // merged launch whose tiles come first in the list.
     std::vector<int> sizes;
     for (const auto &S : b->slots)
         if (S.used) sizes.push_back(S.tables->t.tile_vars);
     std::sort(sizes.begin(), sizes.end());
     sizes.erase(std::unique(sizes.begin(), sizes.end()), sizes.end());
-    size_t k = 0;
+    struct Pending {
+        heom_batch::Group g;
+        std::vector<BatchTile> tiles;
+    };
+    std::vector<Pending> pend;
     for (int m = 1; m <= HEOM_MAX_M; ++m)
         for (int tv : sizes)
             for (int top = 0; top < 2; ++top) {
-                const size_t first = k;
-                uint32_t lds = 0;
+                Pending P{{m, top != 0, (uint32_t)tv, 0u, 0u, 0u}, {}};
                 for (size_t i = 0; i < ns; ++i) {
                     const BatchSlotHost &S = b->slots[i];
                     if (!S.used || S.tables->t.m != m || S.tables->t.tile_vars != tv) continue;
@@ -1317,12 +1460,50 @@ int heom_batch_commit(heom_batch *b, void *dev, size_t bytes, void *stream) {
                     const uint32_t T = (uint32_t)t.tiles.size();
                     const uint32_t split = (t.top_tile > 0 && t.top_tile < T) ? t.top_tile : T;
                     const uint32_t j0 = top ? split : 0, j1 = top ? T : split;
-                    for (uint32_t j = j0; j < j1; ++j) tl[k++] = BatchTile{(uint32_t)i, j};
-                    if (j1 > j0) lds = std::max<uint32_t>(lds, t.lds_bytes);
+                    for (uint32_t j = j0; j < j1; ++j) P.tiles.push_back(BatchTile{(uint32_t)i, top ? (j | BTILE_TOP) : j});
+                    if (j1 > j0) P.g.lds = std::max<uint32_t>(P.g.lds, t.lds_bytes);
                 }
-                if (k > first)
-                    b->groups.push_back({m, top != 0, (uint32_t)tv, lds, (uint32_t)first, (uint32_t)(k - first)});
+                if (!P.tiles.empty()) pend.push_back(std::move(P));
             }
+    std::vector<size_t> order(pend.size());
+    for (size_t q = 0; q < order.size(); ++q) order[q] = q;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](size_t x, size_t y) { return pend[x].tiles.size() < pend[y].tiles.size(); });
+    std::vector<char> merged(pend.size(), 0);
+    size_t mtiles = 0, mcount = 0;
+    for (size_t q : order) {
+        if (pend[q].g.m > MERGE_MAX_M) continue;
+        if (mtiles + pend[q].tiles.size() > (size_t)b->merge_tiles) break;
+        merged[q] = 1;
+        mtiles += pend[q].tiles.size();
+        ++mcount;
+    }
+    if (mcount < 2) std::fill(merged.begin(), merged.end(), 0);
+    size_t k = 0;
+    if (mcount >= 2) {
+        heom_batch::Group M{0, false, 64u, 0u, 0u, 0u};
+        for (size_t q = 0; q < pend.size(); ++q)
+            if (merged[q]) {
+                for (const auto &bt : pend[q].tiles) tl[k++] = bt;
+                M.block = std::max(M.block, pend[q].g.block);
+                M.lds = std::max(M.lds, pend[q].g.lds);
+            }
+        M.count = (uint32_t)k;
+        b->groups.push_back(M);
+    }
+    for (size_t q = 0; q < pend.size(); ++q) {
+        if (merged[q]) continue;
+        heom_batch::Group G = pend[q].g;
+        G.first = (uint32_t)k;
+        for (const auto &bt : pend[q].tiles) tl[k++] = bt;
+        G.count = (uint32_t)(k - G.first);
+        b->groups.push_back(G);
+    }
+    b->ctr_off = tile_off + ((sizeof(BatchTile) * k + 255) & ~(size_t)255);   // counter = 0 in img
+    if (b->gexec) {                        // the captured launches name the old layout
+        HIP_TRY(hipGraphExecDestroy(b->gexec));
+        b->gexec = nullptr;
+    }
     hipStream_t s = static_cast<hipStream_t>(stream);
     HIP_TRY(hipMemcpyAsync(dev, img.data(), need, hipMemcpyHostToDevice, s));
     // Row 0 of a new slot's observables: the initial state, evaluated with
@@ -1348,13 +1529,17 @@ int heom_batch_propagate(heom_batch *b, int64_t nsteps, int precision, void *str
     if (nsteps < 0) return fail(HEOM_E_INVAL, "nsteps < 0");
     if (precision != HEOM_FP64 && precision != HEOM_FP32) return fail(HEOM_E_INVAL, "unknown precision");
     hipStream_t s = static_cast<hipStream_t>(stream);
-    const uint32_t policy = 6u;
-    for (int64_t st = 1; st <= nsteps; ++st)
-        for (int stage = 0; stage < 4; ++stage) {
-            int rc = precision == HEOM_FP64 ? batch_launch<HEOM_FP64>(b, s, stage, st, policy)
-                                            : batch_launch<HEOM_FP32>(b, s, stage, st, policy);
-            if (rc) return rc;
-        }
+    int64_t done = 0;
+    // Whole graphs of graph_steps steps where possible (not on the null
+    // stream, which cannot be captured), single launches for the rest.
+    const int64_t K = b->graph_steps;
+    if (K > 0 && s != nullptr && nsteps >= K) {
+        if (!b->gexec || b->gprec != precision)
+            if (int rc = batch_capture(b, s, precision)) return rc;
+        for (; done + K <= nsteps; done += K) HIP_TRY(hipGraphLaunch(b->gexec, s));
+    }
+    for (; done < nsteps; ++done)
+        if (int rc = batch_step(b, s, precision)) return rc;
     b->steps_since_commit += nsteps;
     for (auto &S : b->slots)
         if (S.used) S.steps += nsteps;
@@ -1364,6 +1549,23 @@ int heom_batch_propagate(heom_batch *b, int64_t nsteps, int precision, void *str
 int heom_batch_slot_steps(const heom_batch *b, int32_t slot, int64_t *steps) {
     if (!b || !steps || slot < 0 || (size_t)slot >= b->slots.size()) return fail(HEOM_E_INVAL, "bad argument");
     *steps = b->slots[(size_t)slot].steps;
+    return HEOM_OK;
+}
+
+int heom_batch_set_graph(heom_batch *b, int32_t steps) {
+    if (!b || steps < 0 || steps > 4096) return fail(HEOM_E_INVAL, "bad batch or graph step count");
+    if (steps != b->graph_steps && b->gexec) {
+        HIP_TRY(hipGraphExecDestroy(b->gexec));
+        b->gexec = nullptr;
+    }
+    b->graph_steps = steps;
+    return HEOM_OK;
+}
+
+int heom_batch_set_merge(heom_batch *b, int32_t max_tiles) {
+    if (!b || max_tiles < 0) return fail(HEOM_E_INVAL, "bad batch or tile count");
+    b->merge_tiles = max_tiles;
+    b->committed = false;
     return HEOM_OK;
 }
 

@@ -32,7 +32,7 @@ SYMBOLS = ["heom_build_tables", "heom_set_params", "heom_table_info", "heom_uplo
            "heom_set_tuning", "heom_get_tuning", "heom_work_status", "heom_params_bytes",
            "heom_upload_params", "heom_batch_create", "heom_batch_set_slot", "heom_batch_clear_slot",
            "heom_batch_device_bytes", "heom_batch_commit", "heom_batch_propagate", "heom_batch_slot_steps",
-           "heom_batch_free"]
+           "heom_batch_set_graph", "heom_batch_set_merge", "heom_batch_free"]
 
 
 class HeomError(RuntimeError):
@@ -101,6 +101,8 @@ def _load():
         "heom_batch_commit": [vp, vp, ctypes.c_size_t, vp],
         "heom_batch_propagate": [vp, i64, ctypes.c_int, vp],
         "heom_batch_slot_steps": [vp, ctypes.c_int32, ctypes.POINTER(i64)],
+        "heom_batch_set_graph": [vp, ctypes.c_int32],
+        "heom_batch_set_merge": [vp, ctypes.c_int32],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -353,6 +355,14 @@ class Batch:
 
     def propagate(self, nsteps: int, precision: int = HEOM_FP64, stream=None):
         _check(LIB.heom_batch_propagate(self._h, int(nsteps), int(precision), _stream(stream)))
+
+    def set_graph(self, steps: int):
+        """Replay groups of `steps` RK4 steps from a captured HIP graph (0 = off)."""
+        _check(LIB.heom_batch_set_graph(self._h, int(steps)))
+
+    def set_merge(self, max_tiles: int):
+        """One launch per stage for batches of at most max_tiles tiles (0 = never)."""
+        _check(LIB.heom_batch_set_merge(self._h, int(max_tiles)))
 
     def slot_steps(self, slot: int) -> int:
         n = ctypes.c_int64()

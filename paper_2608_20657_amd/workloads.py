@@ -134,6 +134,21 @@ def config_paper_shape(N: int, d: int = 0) -> Problem:
 PAPER_SHAPE_DT = 0.5
 
 
+def config_paper_static(N: int, d: int = 0) -> Problem:
+    """The paper's static-disorder runs (Sec. VIII, static energetic
+    disorder), in rad/fs: Gaussian site disorder sigma = 25 cm^-1 as a
+    non-decaying channel (c = sigma^2, nu = 0) beside the Drude-Lorentz
+    channel of config_paper_shape (with its terminator), m = 2, L = 14,
+    Omega_R = 100 cm^-1 with g = Omega_R / (2 sqrt N), resonant at
+    10000 cm^-1, dt = 0.5 fs."""
+    f = CM_TO_RAD_PER_FS
+    base = config_paper_shape(N, d)
+    s2 = complex((25.0 * f) ** 2, 0.0)
+    return Problem(N=N, m=2, L=14, d=d, c=[base.c[0], s2], c_check=[base.c_check[0], s2],
+                   nu=[base.nu[0], 0.0], eps=base.eps, omega_c=base.omega_c,
+                   g=100.0 * f / (2.0 * math.sqrt(N)), kappa=0.0, terminator=base.terminator)
+
+
 def _matsubara_pole_too_close(gam: float, m: int, kT: float) -> bool:
     for k in range(1, m):
         vk = 2.0 * math.pi * k * kT

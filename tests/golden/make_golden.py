@@ -13,6 +13,9 @@ Workloads:
       rad/fs units) at N=5, upper-polariton start, dt=0.5 fs, 400 steps
   paper_n3_superposition -- the same at N=3 with one distinguished molecule,
       rho(0) from sqrt(0.3)|e_1> + sqrt(0.7)|c>, dt=0.5 fs, 400 steps
+  paper_static_n3_up -- the paper's static-disorder workload (Drude-Lorentz +
+      a zero-rate channel, m=2, L=14) at N=3, upper-polariton start,
+      dt=0.5 fs, 400 steps
 """
 import json
 import math
@@ -36,6 +39,8 @@ RUNS = {
                         problem=lambda: W.config_paper_shape(5, 0)),
     "paper_n3_superposition": dict(dt=W.PAPER_SHAPE_DT, steps=400, every=20, state="site1_cavity",
                                    problem=lambda: W.config_paper_shape(3, 1)),
+    "paper_static_n3_up": dict(dt=W.PAPER_SHAPE_DT, steps=400, every=20, state="upper_polariton",
+                               problem=lambda: W.config_paper_static(3, 0)),
 }
 
 

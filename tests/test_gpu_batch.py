@@ -42,15 +42,19 @@ def solo(T, torch, tier0, dt, steps, every, precision):
 
 
 PROBS = [(5, 2, 3, 1, "site1"), (9, 1, 5, 0, "upper_polariton"), (7, 3, 3, 0, "photon"),
-         (64, 2, 6, 1, "site1"), (12, 4, 3, 0, "photon"), (4, 1, 2, 2, "site1")]
+         (64, 2, 6, 1, "site1"), (12, 4, 3, 0, "photon"), (4, 1, 2, 2, "site1"), (6, 5, 2, 0, "photon")]
 
 
-@pytest.mark.parametrize("precision", [0, 1])
-def test_batch_equals_solo(precision):
+@pytest.mark.parametrize("precision,merge", [(0, 16384), (1, 16384), (0, 0), (1, 0), (0, 40)])
+def test_batch_equals_solo(precision, merge):
+    """merge 16384: the groups with m <= 4 run as one launch per stage, the
+    m = 5 group on its own; merge 0: one launch per group; merge 40: only
+    the smallest groups are merged."""
     from paper_2608_20657_amd import heom
     import torch
     steps, every = 37, 5
     batch = heom.Batch(len(PROBS) + 2)
+    batch.set_merge(merge)
     items = []
     for i, (N, m, L, d, state) in enumerate(PROBS):
         p = W.random_problem(N, m, L, d, seed=i + 1, loss=True)
@@ -58,7 +62,7 @@ def test_batch_equals_solo(precision):
         t0 = named_tier0(T, p, state)
         dt = 0.02 + 0.005 * i
         y, work, obs = make_slot(T, torch, t0, every, steps // every + 1)
-        batch.set_slot((3 * i) % (len(PROBS) + 2), T, y, work, dt, obs=obs, obs_every=every)
+        batch.set_slot((2 * i + 1) % (len(PROBS) + 2), T, y, work, dt, obs=obs, obs_every=every)
         items.append((T, p, t0, dt, y, obs))
     batch.commit(torch, torch.cuda.current_stream())
     batch.propagate(steps, precision, torch.cuda.current_stream())
@@ -157,3 +161,68 @@ def test_batch_slot_against_oracle():
     got = obs.cpu().numpy().reshape(-1, 10)
     for j in range(9):
         assert np.abs(got[:, j] - ref[:, j]).max() <= 1e-10 * max(np.abs(ref[:, j]).max(), 1e-300)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_graph_replays_equal_direct_launches(precision):
+    """Steps replayed from a captured HIP graph give bitwise the states and
+    observable rows of direct launches: several replays in a row with other
+    device work and synchronizations between them, a remainder launched
+    directly, and a re-capture after a slot changes."""
+    from paper_2608_20657_amd import heom
+    import torch
+    stream = torch.cuda.Stream()
+    shapes = [(5, 2, 3, 1, "site1"), (9, 1, 5, 0, "upper_polariton"), (64, 2, 6, 1, "site1"), (7, 3, 3, 0, "photon")]
+    every, cap = 3, 40
+    runs = []
+    for graph in (4, 0):
+        b = heom.Batch(len(shapes) + 1)
+        b.set_graph(graph)
+        slots = []
+        with torch.cuda.stream(stream):
+            for i, (N, m, L, d, state) in enumerate(shapes):
+                p = W.random_problem(N, m, L, d, seed=40 + i, loss=True)
+                T, _ = upload(p)
+                t0 = named_tier0(T, p, state)
+                y, work, obs = make_slot(T, torch, t0, every, cap)
+                b.set_slot(i, T, y, work, 0.02, obs=obs, obs_every=every)
+                slots.append((T, y, obs))
+        torch.cuda.synchronize()
+        b.commit(torch, stream)
+        runs.append((b, slots))
+    scratch = torch.ones(1 << 20, dtype=torch.float64, device="cuda")
+    for rep in range(3):
+        for b, _ in runs:
+            b.propagate(9, precision, stream)          # two replays of four steps and one direct step
+        stream.synchronize()
+        scratch.mul_(1.5).add_(rep)                    # other device work between the replays
+        torch.cuda.synchronize()
+        for sa, sb in zip(runs[0][1], runs[1][1]):
+            assert np.array_equal(sa[1].cpu().numpy(), sb[1].cpu().numpy()), rep
+            assert np.array_equal(sa[2].cpu().numpy(), sb[2].cpu().numpy()), rep
+    # a new slot: both batches re-commit (the graph is captured again) and go on
+    p = W.random_problem(6, 2, 4, 0, seed=77, loss=True)
+    extra = []
+    for b, slots in runs:
+        T, _ = upload(p)
+        t0 = named_tier0(T, p, "photon")
+        with torch.cuda.stream(stream):
+            y, work, obs = make_slot(T, torch, t0, every, cap)
+        torch.cuda.synchronize()
+        b.set_slot(len(shapes), T, y, work, 0.03, obs=obs, obs_every=every)
+        b.commit(torch, stream)
+        b.propagate(13, precision, stream)
+        extra.append((y, obs))
+    stream.synchronize()
+    for sa, sb in zip(runs[0][1], runs[1][1]):
+        assert np.array_equal(sa[1].cpu().numpy(), sb[1].cpu().numpy())
+        assert np.array_equal(sa[2].cpu().numpy(), sb[2].cpu().numpy())
+    assert np.array_equal(extra[0][0].cpu().numpy(), extra[1][0].cpu().numpy())
+    assert np.array_equal(extra[0][1].cpu().numpy(), extra[1][1].cpu().numpy())
+    assert runs[0][0].slot_steps(2) == 40 and runs[0][0].slot_steps(len(shapes)) == 13
+    # the graph-replayed trajectory is the solo one
+    T, y, obs = runs[0][1][1]
+    t0 = named_tier0(T, T.problem, "upper_polariton")
+    ys, os_ = solo(T, torch, t0, 0.02, 40, every, precision)
+    assert np.array_equal(y.cpu().numpy(), ys)
+    assert np.array_equal(obs.cpu().numpy().reshape(-1, 10)[:40 // every + 1], os_)

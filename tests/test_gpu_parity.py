@@ -84,11 +84,12 @@ def test_rhs_largest_structure_sampled():
         assert abs(got[i] - want) <= 1e-13 * scale + 1e-300, i
 
 
-@pytest.mark.parametrize("d", [0, 1])
-def test_rhs_paper_shape_sampled(d):
+@pytest.mark.parametrize("make,d", [(W.config_paper_shape, 0), (W.config_paper_shape, 1), (W.config_paper_static, 0)])
+def test_rhs_paper_shape_sampled(make, d):
     """The paper's L=25 workload at N=10^12 (saturated: 306,751 or
-    1,715,600 unique variables), rows sampled against the oracle."""
-    p = W.config_paper_shape(10 ** 12, d)
+    1,715,600 unique variables) and its static-disorder workload (m=2,
+    L=14: 1,820,361), rows sampled against the oracle."""
+    p = make(10 ** 12, d)
     T, torch = upload(p)
     n = T.info()["n_var"]
     y = W.random_vector(n, 11 + d)
@@ -178,13 +179,15 @@ def _golden(name):
     return json.load(open(path))
 
 
-PAPER_RUNS = {"paper_n5_up": (5, 0), "paper_n3_superposition": (3, 1)}
+PAPER_RUNS = {"paper_n5_up": (W.config_paper_shape, 5, 0), "paper_n3_superposition": (W.config_paper_shape, 3, 1),
+              "paper_static_n3_up": (W.config_paper_static, 3, 0)}
 
 
 def _problem_and_tier0(name, T_of, state):
     """Problem of a golden run and its tier-0 block on tables T_of(p)."""
     if name in PAPER_RUNS:
-        p = W.config_paper_shape(*PAPER_RUNS[name])
+        make, N, d = PAPER_RUNS[name]
+        p = make(N, d)
     else:
         p = W.WORKLOADS[name]()
     T, torch = T_of(p)
@@ -195,7 +198,7 @@ def _problem_and_tier0(name, T_of, state):
     return p, T, torch, t0
 
 
-GOLDEN_RUNS = ["localized", "saturated", "paper_n5_up", "paper_n3_superposition"]
+GOLDEN_RUNS = ["localized", "saturated", "paper_n5_up", "paper_n3_superposition", "paper_static_n3_up"]
 
 
 @pytest.mark.parametrize("name", GOLDEN_RUNS)
