@@ -213,7 +213,7 @@ def batched_section(torch, steps, n=512, seed=0, dt=0.02):
 POP_COLS = [1, 2, 4, 5, 6]
 
 
-def serving_point(torch, rate, window, deadline, seed=1, precision=1, budget_gib=256.0,
+def serving_point(torch, rate, window, deadline, seed=1, precision=0, budget_gib=256.0,
                   lanes=(1 << 20,), capacity=(256, 32), fifo=True):
     """Poisson arrivals of propagation requests (problems drawn as in the
     batched workload, plus a horizon of U{1000..20000} steps, obs every 100
@@ -273,10 +273,12 @@ def main():
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--batched-steps", type=int, default=5)
     ap.add_argument("--no-batched", action="store_true")
-    ap.add_argument("--serve-rate", type=float, default=1.0)
-    ap.add_argument("--serve-window", type=float, default=15.0)
-    ap.add_argument("--serve-deadline", type=float, default=30.0)
+    ap.add_argument("--serve-rate", type=float, default=0.5)
+    ap.add_argument("--serve-window", type=float, default=20.0)
+    ap.add_argument("--serve-deadline", type=float, default=40.0)
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-precision", choices=["fp64", "fp32"], default="fp64",
+                    help="arithmetic of the continuous-batching server (the plain baseline is always FP64)")
     ap.add_argument("--serve-sweep", type=str, default="",
                     help="comma-separated arrival rates: print one serving JSON line per rate and exit")
     ap.add_argument("--calibrate-copy-mb", type=int, default=0,
@@ -297,7 +299,8 @@ def main():
     precision = 0 if args.precision == "fp64" else 1
     if args.serve_sweep:
         for r in [float(x) for x in args.serve_sweep.split(",") if x]:
-            rec = serving_point(torch, r, args.serve_window, args.serve_deadline)
+            rec = serving_point(torch, r, args.serve_window, args.serve_deadline,
+                                precision=0 if args.serve_precision == "fp64" else 1)
             print(json.dumps({"serving_sweep_point": rec}), flush=True)
         return
     if args.calibrate_copy_mb:
@@ -403,7 +406,8 @@ def main():
     if not args.no_batched:
         out["batched"] = batched_section(torch, args.batched_steps)
     if not args.no_serve:
-        out["serving"] = serving_point(torch, args.serve_rate, args.serve_window, args.serve_deadline)
+        out["serving"] = serving_point(torch, args.serve_rate, args.serve_window, args.serve_deadline,
+                                       precision=0 if args.serve_precision == "fp64" else 1)
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(p, lambda i: 1.0 if i == 1 else 0.0, dt, args.cpu_seconds)

@@ -317,8 +317,9 @@ int heom_batch_propagate(heom_batch *b, int64_t nsteps, int precision, void *str
 int heom_batch_set_graph(heom_batch *b, int32_t steps);
 
 /* Launch shape: the batch's tiles fall into groups of one m, tile size and
- * tier class. The smallest groups with m <= 4, up to max_tiles tiles in
- * all, are run as one launch per RK4 stage (each workgroup picks the kernel
+ * tier class. The smallest groups with m <= 4 and at most max_tiles/8
+ * tiles each, up to max_tiles tiles in all, are run as one launch per RK4
+ * stage (each workgroup picks the kernel
  * variant of its slot's m and tier class); every other group has its own
  * launch. Small problems are bound by the latency of dependent launches,
  * which the merged launch avoids; large groups keep their own kernels, whose

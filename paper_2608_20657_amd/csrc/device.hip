@@ -34,6 +34,31 @@ struct BatchSlotHost {
     int64_t obs_every = 0, obs_cap = 0, steps = 0;
 };
 
+// One slot of a batch: an uploaded structure image, a params block (the
+// head of an image: InstParams + coefficient tables) and the slot's own
+// state, work and observable buffers.
+struct SlotRec {
+    const unsigned char *img;
+    const unsigned char *params;
+    // table sections of img and the coefficient tables of params, resolved on
+    // the host so that a workgroup's first loads do not wait for each other
+    const PatHdr *hdr;
+    const CatRec *cat;
+    const uint32_t *gidx;
+    const TileRec *tiles;
+    const VarRec *vrec;
+    const double *lut;
+    double2 *y, *w0, *w1;     // FP64 stage vectors
+    float2 *u1, *u2, *u3;     // FP32 increments
+    double *obs;
+    int64_t obs_every, obs_cap, step0;
+    double dt;
+};
+struct BatchTile {
+    uint32_t slot, tile;   // tile | BTILE_TOP for a tile of the top tier
+};
+constexpr uint32_t BTILE_TOP = 0x80000000u;
+
 struct heom_batch {
     std::vector<BatchSlotHost> slots;
     bool committed = false;
@@ -43,10 +68,13 @@ struct heom_batch {
     // One launch per group: tiles of one m, one tile size and one tier class
     // (top-tier tiles have no up moves and run a lighter kernel variant).
     struct Group {
-        int m;       // 0: every tile of the batch in one launch (batch_stage_merged)
+        int m;       // 0: the small groups' tiles in one launch (batch_stage_merged)
         bool top;
         uint32_t block, lds, first, count;
+        int32_t slot;     // >= 0: tiles tile0.. of this slot alone (batch_stage_single)
+        uint32_t tile0;
     };
+    std::vector<SlotRec> recs;        // host copy of the committed slot records
     std::vector<Group> groups;
     // Steps replayed from a captured HIP graph (0 = launch every kernel).
     int32_t graph_steps = 0;
@@ -580,22 +608,6 @@ __global__ __launch_bounds__(MAX_TILE) void persistent_kernel(Dev D, PersistArgs
 }
 
 // ---------------------------------------------------------------- batches
-// One slot of a batch: an uploaded structure image, a params block (the
-// head of an image: InstParams + coefficient tables) and the slot's own
-// state, work and observable buffers.
-struct SlotRec {
-    const unsigned char *img;
-    const unsigned char *params;
-    double2 *y, *w0, *w1;     // FP64 stage vectors
-    float2 *u1, *u2, *u3;     // FP32 increments
-    double *obs;
-    int64_t obs_every, obs_cap, step0;
-    double dt;
-};
-struct BatchTile {
-    uint32_t slot, tile;   // tile | BTILE_TOP for a tile of the top tier
-};
-constexpr uint32_t BTILE_TOP = 0x80000000u;
 
 // A pointer read from memory has no known address space, so accesses
 // through it would be flat instructions (which also hold up every LDS wait)
@@ -622,13 +634,19 @@ struct BatchCtx {
 };
 
 template <int PREC>
-__device__ __forceinline__ BatchCtx batch_ctx(const SlotRec *slots, uint32_t slot, uint32_t tile, int s,
-                                              const int64_t *ctr, uint32_t policy) {
+__device__ __forceinline__ BatchCtx batch_ctx(const SlotRec &rec, uint32_t tile, int s, int64_t *ctr,
+                                              uint32_t policy) {
     BatchCtx c;
     SlotRec &R = c.R;
-    R = slots[slot];
+    R = rec;
     R.img = as_global(R.img);
     R.params = as_global(R.params);
+    R.hdr = as_global(R.hdr);
+    R.cat = as_global(R.cat);
+    R.gidx = as_global(R.gidx);
+    R.tiles = as_global(R.tiles);
+    R.vrec = as_global(R.vrec);
+    R.lut = as_global(R.lut);
     R.y = as_global(R.y);
     R.w0 = as_global(R.w0);
     R.w1 = as_global(R.w1);
@@ -639,18 +657,20 @@ __device__ __forceinline__ BatchCtx batch_ctx(const SlotRec *slots, uint32_t slo
     const InstParams &P = *reinterpret_cast<const InstParams *>(R.params);
     Dev &D = c.D;
     D.ip = &P;
-    D.lut = reinterpret_cast<const double *>(R.params + P.off_lut);
-    D.hdr = reinterpret_cast<const PatHdr *>(R.img + P.off_hdr);
-    D.cat = reinterpret_cast<const CatRec *>(R.img + P.off_cat);
-    D.gidx = reinterpret_cast<const uint32_t *>(R.img + P.off_gidx);
-    D.tiles = reinterpret_cast<const TileRec *>(R.img + P.off_tile);
-    D.vrec = reinterpret_cast<const VarRec *>(R.img + P.off_vrec);
+    D.lut = R.lut;
+    D.hdr = R.hdr;
+    D.cat = R.cat;
+    D.gidx = R.gidx;
+    D.tiles = R.tiles;
+    D.vrec = R.vrec;
     c.TR = D.tiles[tile];
     const double h = R.dt;
-    // steps of this slot so far, this one included; the counter (steps of the
-    // batch since the last commit) is advanced on the device, so a captured
-    // graph of steps replays with the right observable rows
-    const int64_t gst = R.step0 + *as_global(ctr) + 1;
+    // Steps of this slot so far, this one included, for the observable row
+    // of the last stage. The counter (steps of the batch since the last
+    // commit, this one included) is advanced on the device by the first
+    // launch of each step's first stage, so a captured graph of steps
+    // replays with the right rows; only the last stage reads it.
+    const int64_t gst = s == 3 ? R.step0 + *as_global(ctr) : 0;
     StageArgs &a = c.a;
     a = StageArgs{};
     a.policy = policy;
@@ -698,10 +718,23 @@ __device__ __forceinline__ void batch_tile(const BatchCtx &c, unsigned char *sme
 // instance holds only the registers of its own stage pattern.
 template <int M, int PREC, bool TOP, int SV>
 __global__ __launch_bounds__(MAX_TILE) void batch_stage_kernel(const SlotRec *slots, const BatchTile *btiles, int s,
-                                                             const int64_t *ctr, uint32_t policy) {
+                                                             int64_t *ctr, uint32_t policy, uint32_t advance) {
     extern __shared__ __align__(16) unsigned char smem[];
     const BatchTile B = btiles[blockIdx.x];
-    const BatchCtx c = batch_ctx<PREC>(slots, B.slot, B.tile & ~BTILE_TOP, s, ctr, policy);
+    if (advance && blockIdx.x == 0 && threadIdx.x == 0) *as_global(ctr) += 1;
+    const BatchCtx c = batch_ctx<PREC>(slots[B.slot], B.tile & ~BTILE_TOP, s, ctr, policy);
+    batch_tile<M, PREC, TOP, SV>(c, smem);
+}
+
+// The tiles tile0.. of one slot, whose record comes in the kernel arguments
+// (as a state's tables do for stage_kernel): no list or record lookups
+// before the first loads. For slots large enough to fill launches alone.
+template <int M, int PREC, bool TOP, int SV>
+__global__ __launch_bounds__(MAX_TILE) void batch_stage_single(SlotRec R, uint32_t tile0, int s, int64_t *ctr,
+                                                             uint32_t policy, uint32_t advance) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    if (advance && blockIdx.x == 0 && threadIdx.x == 0) *as_global(ctr) += 1;
+    const BatchCtx c = batch_ctx<PREC>(R, tile0 + blockIdx.x, s, ctr, policy);
     batch_tile<M, PREC, TOP, SV>(c, smem);
 }
 
@@ -713,11 +746,12 @@ __global__ __launch_bounds__(MAX_TILE) void batch_stage_kernel(const SlotRec *sl
 constexpr int MERGE_MAX_M = 4;
 template <int PREC, int SV>
 __global__ __launch_bounds__(MAX_TILE) void batch_stage_merged(const SlotRec *slots, const BatchTile *btiles, int s,
-                                                             const int64_t *ctr, uint32_t policy) {
+                                                             int64_t *ctr, uint32_t policy, uint32_t advance) {
     extern __shared__ __align__(16) unsigned char smem[];
     const BatchTile B = btiles[blockIdx.x];
+    if (advance && blockIdx.x == 0 && threadIdx.x == 0) *as_global(ctr) += 1;
     const bool top = (B.tile & BTILE_TOP) != 0;
-    const BatchCtx c = batch_ctx<PREC>(slots, B.slot, B.tile & ~BTILE_TOP, s, ctr, policy);
+    const BatchCtx c = batch_ctx<PREC>(slots[B.slot], B.tile & ~BTILE_TOP, s, ctr, policy);
     switch (c.D.ip->m * 2 + (top ? 1 : 0)) {
         case 2: batch_tile<1, PREC, false, SV>(c, smem); break;
         case 3: batch_tile<1, PREC, true, SV>(c, smem); break;
@@ -744,13 +778,20 @@ __global__ void zero_kernel(double2 *y, uint32_t n) {
         y[i] = make_double2(0.0, 0.0);
 }
 
+// States of at least this many tiles run their top tier as a second launch
+// with the kernel variant that has no up moves (fewer registers, more waves);
+// for smaller ones the extra launch costs more than it saves.
+constexpr uint32_t TOP_SPLIT_TILES = 2048;
+// Slots of at least this many tiles get launches of their own in a batch.
+constexpr uint32_t SOLO_TILES = 4096;
+
 template <int M, bool HAS64, bool HAS32, int BASE, bool EXTRA, bool OUT64>
 void launch_m(const HostTables &t, hipStream_t s, StageArgs a) {
     a.policy = (uint32_t)t.tune.cache_policy;
     const uint32_t T = (uint32_t)t.tiles.size();
     // Large states: the top tier (no up moves) runs in its own launch with a
     // kernel that has no up-move slots, fewer registers and more waves.
-    const uint32_t split = (T >= 2048 && t.top_tile > 0 && t.top_tile < T) ? t.top_tile : T;
+    const uint32_t split = (T >= TOP_SPLIT_TILES && t.top_tile > 0 && t.top_tile < T) ? t.top_tile : T;
     a.tile0 = 0;
     hipLaunchKernelGGL((stage_kernel<M, HAS64, HAS32, BASE, EXTRA, OUT64, false>), dim3(split),
                        dim3(t.tile_vars), t.lds_bytes, s, dev_view(t), a, t.tune.xcd_map);
@@ -841,51 +882,62 @@ int check_dev(const void *p, const char *name) {
 }
 
 template <int M, int PREC, bool TOP>
-void batch_launch_group(const heom_batch::Group &g, hipStream_t s, const SlotRec *recs, const BatchTile *first,
-                        int stage, const int64_t *ctr, uint32_t policy) {
+void batch_launch_group(const heom_batch *b, const heom_batch::Group &g, hipStream_t s, const SlotRec *recs,
+                        const BatchTile *first, int stage, int64_t *ctr, uint32_t policy, uint32_t advance) {
     const dim3 grid(g.count), block(g.block);
     const int sv = stage == 0 ? 0 : (PREC == HEOM_FP64 ? 1 : (stage < 3 ? 1 : 2));
+    if (g.slot >= 0) {
+        const SlotRec &R = b->recs[(size_t)g.slot];
+        const uint32_t tile0 = g.tile0;
+        if (sv == 0)
+            hipLaunchKernelGGL((batch_stage_single<M, PREC, TOP, 0>), grid, block, g.lds, s, R, tile0, stage, ctr,
+                               policy, advance);
+        else if (sv == 1)
+            hipLaunchKernelGGL((batch_stage_single<M, PREC, TOP, 1>), grid, block, g.lds, s, R, tile0, stage, ctr,
+                               policy, advance);
+        else if (PREC == HEOM_FP32)
+            hipLaunchKernelGGL((batch_stage_single<M, PREC, TOP, 2>), grid, block, g.lds, s, R, tile0, stage, ctr,
+                               policy, advance);
+        return;
+    }
     if (sv == 0)
         hipLaunchKernelGGL((batch_stage_kernel<M, PREC, TOP, 0>), grid, block, g.lds, s, recs, first, stage, ctr,
-                           policy);
+                           policy, advance);
     else if (sv == 1)
         hipLaunchKernelGGL((batch_stage_kernel<M, PREC, TOP, 1>), grid, block, g.lds, s, recs, first, stage, ctr,
-                           policy);
+                           policy, advance);
     else if (PREC == HEOM_FP32)
         hipLaunchKernelGGL((batch_stage_kernel<M, PREC, TOP, 2>), grid, block, g.lds, s, recs, first, stage, ctr,
-                           policy);
+                           policy, advance);
 }
 
-// Advance the batch's device step counter by one (a single thread, after
-// the last stage of a step).
-__global__ void tick_kernel(int64_t *ctr) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) ctr[0] += 1;
-}
 
 template <int PREC>
 int batch_launch(const heom_batch *b, hipStream_t s, int stage, uint32_t policy) {
     const SlotRec *recs = static_cast<const SlotRec *>(b->dev);
     const size_t tile_off = (sizeof(SlotRec) * b->slots.size() + 255) & ~(size_t)255;
     const BatchTile *tl = reinterpret_cast<const BatchTile *>(static_cast<const unsigned char *>(b->dev) + tile_off);
-    const int64_t *ctr = reinterpret_cast<const int64_t *>(static_cast<const unsigned char *>(b->dev) + b->ctr_off);
+    int64_t *ctr = reinterpret_cast<int64_t *>(static_cast<unsigned char *>(b->dev) + b->ctr_off);
+    uint32_t advance = stage == 0 ? 1u : 0u;   // the step's first launch advances the counter
     for (const auto &g : b->groups) {
         const BatchTile *first = tl + g.first;
         if (g.m == 0) {
             const dim3 grid(g.count), block(g.block);
             const int sv = stage == 0 ? 0 : (PREC == HEOM_FP64 ? 1 : (stage < 3 ? 1 : 2));
             if (sv == 0)
-                hipLaunchKernelGGL((batch_stage_merged<PREC, 0>), grid, block, g.lds, s, recs, first, stage, ctr, policy);
+                hipLaunchKernelGGL((batch_stage_merged<PREC, 0>), grid, block, g.lds, s, recs, first, stage, ctr, policy, advance);
             else if (sv == 1)
-                hipLaunchKernelGGL((batch_stage_merged<PREC, 1>), grid, block, g.lds, s, recs, first, stage, ctr, policy);
+                hipLaunchKernelGGL((batch_stage_merged<PREC, 1>), grid, block, g.lds, s, recs, first, stage, ctr, policy, advance);
             else if (PREC == HEOM_FP32)
-                hipLaunchKernelGGL((batch_stage_merged<PREC, 2>), grid, block, g.lds, s, recs, first, stage, ctr, policy);
+                hipLaunchKernelGGL((batch_stage_merged<PREC, 2>), grid, block, g.lds, s, recs, first, stage, ctr, policy, advance);
             HIP_TRY(hipGetLastError());
+            advance = 0u;
             continue;
         }
 #define HEOM_BCASE(MM)                                                                         \
     case MM:                                                                                   \
-        if (g.top) batch_launch_group<MM, PREC, true>(g, s, recs, first, stage, ctr, policy);  \
-        else batch_launch_group<MM, PREC, false>(g, s, recs, first, stage, ctr, policy);       \
+        if (g.top) batch_launch_group<MM, PREC, true>(b, g, s, recs, first, stage, ctr, policy, advance);  \
+        else batch_launch_group<MM, PREC, false>(b, g, s, recs, first, stage, ctr, policy, advance);       \
         break;
         switch (g.m) {
             HEOM_BCASE(1) HEOM_BCASE(2) HEOM_BCASE(3) HEOM_BCASE(4)
@@ -894,11 +946,12 @@ int batch_launch(const heom_batch *b, hipStream_t s, int stage, uint32_t policy)
         }
 #undef HEOM_BCASE
         HIP_TRY(hipGetLastError());
+        advance = 0u;
     }
     return HEOM_OK;
 }
 
-// One RK4 step of every slot: four stage launches per group, then the tick.
+// One RK4 step of every slot: four stage launches per group.
 int batch_step(const heom_batch *b, hipStream_t s, int precision) {
     const uint32_t policy = 6u;
     for (int stage = 0; stage < 4; ++stage) {
@@ -906,9 +959,6 @@ int batch_step(const heom_batch *b, hipStream_t s, int precision) {
                                               : batch_launch<HEOM_FP32>(b, s, stage, policy);
         if (rc) return rc;
     }
-    int64_t *ctr = reinterpret_cast<int64_t *>(static_cast<unsigned char *>(b->dev) + b->ctr_off);
-    hipLaunchKernelGGL(tick_kernel, dim3(1), dim3(64), 0, s, ctr);
-    HIP_TRY(hipGetLastError());
     return HEOM_OK;
 }
 
@@ -1422,6 +1472,13 @@ int heom_batch_commit(heom_batch *b, void *dev, size_t bytes, void *stream) {
         SlotRec &R = recs[i];
         R.img = static_cast<const unsigned char *>(t.dev);
         R.params = static_cast<const unsigned char *>(S.params);
+        const Dev D = dev_view(t);
+        R.hdr = D.hdr;
+        R.cat = D.cat;
+        R.gidx = D.gidx;
+        R.tiles = D.tiles;
+        R.vrec = D.vrec;
+        R.lut = reinterpret_cast<const double *>(R.params + reinterpret_cast<const InstParams *>(t.image.data())->off_lut);
         unsigned char *wb = static_cast<unsigned char *>(S.work);
         R.y = static_cast<double2 *>(S.y);
         R.w0 = reinterpret_cast<double2 *>(wb);
@@ -1448,20 +1505,28 @@ int heom_batch_commit(heom_batch *b, void *dev, size_t bytes, void *stream) {
         heom_batch::Group g;
         std::vector<BatchTile> tiles;
     };
-    std::vector<Pending> pend;
+    std::vector<Pending> pend, solo;
     for (int m = 1; m <= HEOM_MAX_M; ++m)
         for (int tv : sizes)
             for (int top = 0; top < 2; ++top) {
-                Pending P{{m, top != 0, (uint32_t)tv, 0u, 0u, 0u}, {}};
+                Pending P{{m, top != 0, (uint32_t)tv, 0u, 0u, 0u, -1, 0u}, {}};
                 for (size_t i = 0; i < ns; ++i) {
                     const BatchSlotHost &S = b->slots[i];
                     if (!S.used || S.tables->t.m != m || S.tables->t.tile_vars != tv) continue;
                     const HostTables &t = S.tables->t;
                     const uint32_t T = (uint32_t)t.tiles.size();
-                    const uint32_t split = (t.top_tile > 0 && t.top_tile < T) ? t.top_tile : T;
+                    // as in heom_propagate: large states run the top tier with its own variant
+                    const uint32_t split = (T >= TOP_SPLIT_TILES && t.top_tile > 0 && t.top_tile < T) ? t.top_tile : T;
                     const uint32_t j0 = top ? split : 0, j1 = top ? T : split;
+                    if (j1 <= j0) continue;
+                    if (T >= SOLO_TILES) {   // a launch of its own, record in the kernel arguments
+                        Pending Q{{m, top != 0, (uint32_t)tv, t.lds_bytes, 0u, 0u, (int32_t)i, j0}, {}};
+                        for (uint32_t j = j0; j < j1; ++j) Q.tiles.push_back(BatchTile{(uint32_t)i, top ? (j | BTILE_TOP) : j});
+                        solo.push_back(std::move(Q));
+                        continue;
+                    }
                     for (uint32_t j = j0; j < j1; ++j) P.tiles.push_back(BatchTile{(uint32_t)i, top ? (j | BTILE_TOP) : j});
-                    if (j1 > j0) P.g.lds = std::max<uint32_t>(P.g.lds, t.lds_bytes);
+                    P.g.lds = std::max<uint32_t>(P.g.lds, t.lds_bytes);
                 }
                 if (!P.tiles.empty()) pend.push_back(std::move(P));
             }
@@ -1472,7 +1537,9 @@ int heom_batch_commit(heom_batch *b, void *dev, size_t bytes, void *stream) {
     std::vector<char> merged(pend.size(), 0);
     size_t mtiles = 0, mcount = 0;
     for (size_t q : order) {
-        if (pend[q].g.m > MERGE_MAX_M) continue;
+        // large groups keep their own launch (and the occupancy of their own
+        // kernel variant); only small ones are worth a shared launch
+        if (pend[q].g.m > MERGE_MAX_M || pend[q].tiles.size() > (size_t)b->merge_tiles / 8) continue;
         if (mtiles + pend[q].tiles.size() > (size_t)b->merge_tiles) break;
         merged[q] = 1;
         mtiles += pend[q].tiles.size();
@@ -1481,7 +1548,7 @@ int heom_batch_commit(heom_batch *b, void *dev, size_t bytes, void *stream) {
     if (mcount < 2) std::fill(merged.begin(), merged.end(), 0);
     size_t k = 0;
     if (mcount >= 2) {
-        heom_batch::Group M{0, false, 64u, 0u, 0u, 0u};
+        heom_batch::Group M{0, false, 64u, 0u, 0u, 0u, -1, 0u};
         for (size_t q = 0; q < pend.size(); ++q)
             if (merged[q]) {
                 for (const auto &bt : pend[q].tiles) tl[k++] = bt;
@@ -1499,6 +1566,14 @@ int heom_batch_commit(heom_batch *b, void *dev, size_t bytes, void *stream) {
         G.count = (uint32_t)(k - G.first);
         b->groups.push_back(G);
     }
+    for (auto &Q : solo) {
+        heom_batch::Group G = Q.g;
+        G.first = (uint32_t)k;
+        for (const auto &bt : Q.tiles) tl[k++] = bt;
+        G.count = (uint32_t)(k - G.first);
+        b->groups.push_back(G);
+    }
+    b->recs.assign(recs, recs + ns);
     b->ctr_off = tile_off + ((sizeof(BatchTile) * k + 255) & ~(size_t)255);   // counter = 0 in img
     if (b->gexec) {                        // the captured launches name the old layout
         HIP_TRY(hipGraphExecDestroy(b->gexec));

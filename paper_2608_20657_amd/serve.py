@@ -428,11 +428,12 @@ class Server:
         reqs = [r for r in sorted(requests, key=lambda r: r.arrival) if window is None or r.arrival <= window]
         self.t0 = self._clock()
         i = 0
-        submitted = 0
+        submitted = []
         while True:
             now = self.now()
             while i < len(reqs) and reqs[i].arrival <= now:
-                submitted += int(self.submit(reqs[i]))
+                if self.submit(reqs[i]):
+                    submitted.append((reqs[i].rid, reqs[i].arrival))
                 i += 1
             more = i < len(reqs)
             busy = self.in_flight() > 0 or bool(self.waiting)
@@ -538,17 +539,29 @@ class Fifo:
             completed += 1
         self.torch.cuda.synchronize()
         elapsed = self.now()
-        submitted = sum(1 for r in reqs if r.arrival <= elapsed)
-        return summarize(self.results, submitted, elapsed, outstanding=submitted - completed)
+        submitted = [(r.rid, r.arrival) for r in reqs if r.arrival <= elapsed]
+        return summarize(self.results, submitted, elapsed, outstanding=len(submitted) - completed)
 
 
 # --------------------------------------------------------------- statistics
 
-def summarize(results: Sequence[Result], submitted: int, elapsed: float, outstanding: int = 0,
+def summarize(results: Sequence[Result], submitted, elapsed: float, outstanding: int = 0,
               busy_ms=None) -> Dict:
+    """Throughput and latency of a run. `submitted`: (rid, arrival) of every
+    request admitted to the queue (or their count). Percentiles are given
+    over the completed requests and, as a lower bound that does not favour
+    a policy that finishes only its short requests, over all submitted ones
+    with each unfinished request counted as waiting until the end of the run."""
     lat = np.array([r.latency for r in results]) if results else np.zeros(0)
+    if isinstance(submitted, int):
+        n_sub, cens = submitted, np.zeros(0)
+    else:
+        done = {r.rid for r in results}
+        n_sub = len(submitted)
+        cens = np.array([elapsed - a for rid, a in submitted if rid not in done])
+    allv = np.concatenate([lat, cens])
     out = {
-        "submitted": int(submitted),
+        "submitted": int(n_sub),
         "completed": len(results),
         "outstanding": int(outstanding),
         "elapsed_s": float(elapsed),
@@ -556,6 +569,8 @@ def summarize(results: Sequence[Result], submitted: int, elapsed: float, outstan
         "p50_latency_s": float(np.percentile(lat, 50)) if lat.size else None,
         "p99_latency_s": float(np.percentile(lat, 99)) if lat.size else None,
         "mean_latency_s": float(lat.mean()) if lat.size else None,
+        "p50_latency_all_lower_bound_s": float(np.percentile(allv, 50)) if allv.size else None,
+        "p99_latency_all_lower_bound_s": float(np.percentile(allv, 99)) if allv.size else None,
     }
     if busy_ms is not None:
         out["lane_busy_ms"] = [float(b) for b in busy_ms]

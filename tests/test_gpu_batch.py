@@ -41,8 +41,11 @@ def solo(T, torch, tier0, dt, steps, every, precision):
     return y.cpu().numpy(), obs.cpu().numpy().reshape(-1, 10)
 
 
+# the last one has launches of its own in a batch (>= 4096 tiles) and runs
+# its top tier with the top-tier kernel variant (>= 2048 tiles)
 PROBS = [(5, 2, 3, 1, "site1"), (9, 1, 5, 0, "upper_polariton"), (7, 3, 3, 0, "photon"),
-         (64, 2, 6, 1, "site1"), (12, 4, 3, 0, "photon"), (4, 1, 2, 2, "site1"), (6, 5, 2, 0, "photon")]
+         (64, 2, 6, 1, "site1"), (12, 4, 3, 0, "photon"), (4, 1, 2, 2, "site1"), (6, 5, 2, 0, "photon"),
+         (10000, 3, 8, 0, "upper_polariton"), (100, 4, 8, 0, "photon")]
 
 
 @pytest.mark.parametrize("precision,merge", [(0, 16384), (1, 16384), (0, 0), (1, 0), (0, 40)])
@@ -62,7 +65,7 @@ def test_batch_equals_solo(precision, merge):
         t0 = named_tier0(T, p, state)
         dt = 0.02 + 0.005 * i
         y, work, obs = make_slot(T, torch, t0, every, steps // every + 1)
-        batch.set_slot((2 * i + 1) % (len(PROBS) + 2), T, y, work, dt, obs=obs, obs_every=every)
+        batch.set_slot((3 * i + 1) % (len(PROBS) + 2), T, y, work, dt, obs=obs, obs_every=every)
         items.append((T, p, t0, dt, y, obs))
     batch.commit(torch, torch.cuda.current_stream())
     batch.propagate(steps, precision, torch.cuda.current_stream())

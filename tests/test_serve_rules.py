@@ -96,3 +96,13 @@ def test_summarize_percentiles():
     assert st["solves_per_s"] == pytest.approx(2.0)
     assert st["p50_latency_s"] == pytest.approx(50.5)
     assert st["p99_latency_s"] == pytest.approx(99.01)
+
+
+def test_summarize_censors_unfinished_requests():
+    # two finished after 1 s, two never finished in a 10 s run (arrived at 0 and 4 s)
+    rs = [S.Result(0, 0.0, 0.0, 1.0, None, 1), S.Result(1, 2.0, 2.0, 3.0, None, 1)]
+    st = S.summarize(rs, [(0, 0.0), (1, 2.0), (2, 0.0), (3, 4.0)], 10.0, outstanding=2)
+    assert st["submitted"] == 4 and st["completed"] == 2
+    assert st["p50_latency_s"] == pytest.approx(1.0)
+    # all latencies: 1, 1, 10, 6 -> median 3.5
+    assert st["p50_latency_all_lower_bound_s"] == pytest.approx(3.5)
