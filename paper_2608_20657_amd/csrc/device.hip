@@ -711,6 +711,14 @@ __device__ __forceinline__ void batch_tile(const BatchCtx &c, unsigned char *sme
     }
 }
 
+// The first launch of a step's first stage advances the batch's step counter
+// (one thread, last thing in the kernel: a store ahead of the record loads
+// would keep the compiler from proving them unclobbered and moving them to
+// the scalar unit).
+__device__ __forceinline__ void advance_counter(int64_t *ctr, uint32_t advance) {
+    if (advance && blockIdx.x == 0 && threadIdx.x == 0) *as_global(ctr) += 1;
+}
+
 // One RK4 stage of every tile of every slot in a tile list (all of one m,
 // one tile size and one tier class). Each variable is computed by the same
 // arithmetic as in stage_kernel, so a problem's trajectory does not depend
@@ -721,9 +729,9 @@ __global__ __launch_bounds__(MAX_TILE) void batch_stage_kernel(const SlotRec *sl
                                                              int64_t *ctr, uint32_t policy, uint32_t advance) {
     extern __shared__ __align__(16) unsigned char smem[];
     const BatchTile B = btiles[blockIdx.x];
-    if (advance && blockIdx.x == 0 && threadIdx.x == 0) *as_global(ctr) += 1;
     const BatchCtx c = batch_ctx<PREC>(slots[B.slot], B.tile & ~BTILE_TOP, s, ctr, policy);
     batch_tile<M, PREC, TOP, SV>(c, smem);
+    advance_counter(ctr, advance);
 }
 
 // The tiles tile0.. of one slot, whose record comes in the kernel arguments
@@ -733,9 +741,9 @@ template <int M, int PREC, bool TOP, int SV>
 __global__ __launch_bounds__(MAX_TILE) void batch_stage_single(SlotRec R, uint32_t tile0, int s, int64_t *ctr,
                                                              uint32_t policy, uint32_t advance) {
     extern __shared__ __align__(16) unsigned char smem[];
-    if (advance && blockIdx.x == 0 && threadIdx.x == 0) *as_global(ctr) += 1;
     const BatchCtx c = batch_ctx<PREC>(R, tile0 + blockIdx.x, s, ctr, policy);
     batch_tile<M, PREC, TOP, SV>(c, smem);
+    advance_counter(ctr, advance);
 }
 
 // The same for a whole batch in one launch per stage, for batches of small
@@ -749,7 +757,6 @@ __global__ __launch_bounds__(MAX_TILE) void batch_stage_merged(const SlotRec *sl
                                                              int64_t *ctr, uint32_t policy, uint32_t advance) {
     extern __shared__ __align__(16) unsigned char smem[];
     const BatchTile B = btiles[blockIdx.x];
-    if (advance && blockIdx.x == 0 && threadIdx.x == 0) *as_global(ctr) += 1;
     const bool top = (B.tile & BTILE_TOP) != 0;
     const BatchCtx c = batch_ctx<PREC>(slots[B.slot], B.tile & ~BTILE_TOP, s, ctr, policy);
     switch (c.D.ip->m * 2 + (top ? 1 : 0)) {
@@ -763,6 +770,7 @@ __global__ __launch_bounds__(MAX_TILE) void batch_stage_merged(const SlotRec *sl
         case 9: batch_tile<4, PREC, true, SV>(c, smem); break;
         default: break;   // excluded when the batch is committed
     }
+    advance_counter(ctr, advance);
 }
 
 __global__ void observables_kernel(Dev D, const double2 *y, double *obs) {
@@ -782,8 +790,6 @@ __global__ void zero_kernel(double2 *y, uint32_t n) {
 // with the kernel variant that has no up moves (fewer registers, more waves);
 // for smaller ones the extra launch costs more than it saves.
 constexpr uint32_t TOP_SPLIT_TILES = 2048;
-// Slots of at least this many tiles get launches of their own in a batch.
-constexpr uint32_t SOLO_TILES = 4096;
 
 template <int M, bool HAS64, bool HAS32, int BASE, bool EXTRA, bool OUT64>
 void launch_m(const HostTables &t, hipStream_t s, StageArgs a) {
@@ -1505,7 +1511,9 @@ int heom_batch_commit(heom_batch *b, void *dev, size_t bytes, void *stream) {
         heom_batch::Group g;
         std::vector<BatchTile> tiles;
     };
-    std::vector<Pending> pend, solo;
+    std::vector<Pending> pend;
+    size_t used = 0;
+    for (const auto &S : b->slots) used += S.used ? 1 : 0;
     for (int m = 1; m <= HEOM_MAX_M; ++m)
         for (int tv : sizes)
             for (int top = 0; top < 2; ++top) {
@@ -1515,16 +1523,13 @@ int heom_batch_commit(heom_batch *b, void *dev, size_t bytes, void *stream) {
                     if (!S.used || S.tables->t.m != m || S.tables->t.tile_vars != tv) continue;
                     const HostTables &t = S.tables->t;
                     const uint32_t T = (uint32_t)t.tiles.size();
-                    // as in heom_propagate: large states run the top tier with its own variant
-                    const uint32_t split = (T >= TOP_SPLIT_TILES && t.top_tile > 0 && t.top_tile < T) ? t.top_tile : T;
+                    // Top-tier tiles run with the top-tier variant: in a batch the extra
+                    // launch is shared by every slot of the group, and small groups are
+                    // merged below. A batch of one slot follows heom_propagate.
+                    const bool split_ok = used > 1 || T >= TOP_SPLIT_TILES;
+                    const uint32_t split = (split_ok && t.top_tile > 0 && t.top_tile < T) ? t.top_tile : T;
                     const uint32_t j0 = top ? split : 0, j1 = top ? T : split;
                     if (j1 <= j0) continue;
-                    if (T >= SOLO_TILES) {   // a launch of its own, record in the kernel arguments
-                        Pending Q{{m, top != 0, (uint32_t)tv, t.lds_bytes, 0u, 0u, (int32_t)i, j0}, {}};
-                        for (uint32_t j = j0; j < j1; ++j) Q.tiles.push_back(BatchTile{(uint32_t)i, top ? (j | BTILE_TOP) : j});
-                        solo.push_back(std::move(Q));
-                        continue;
-                    }
                     for (uint32_t j = j0; j < j1; ++j) P.tiles.push_back(BatchTile{(uint32_t)i, top ? (j | BTILE_TOP) : j});
                     P.g.lds = std::max<uint32_t>(P.g.lds, t.lds_bytes);
                 }
@@ -1564,13 +1569,12 @@ int heom_batch_commit(heom_batch *b, void *dev, size_t bytes, void *stream) {
         G.first = (uint32_t)k;
         for (const auto &bt : pend[q].tiles) tl[k++] = bt;
         G.count = (uint32_t)(k - G.first);
-        b->groups.push_back(G);
-    }
-    for (auto &Q : solo) {
-        heom_batch::Group G = Q.g;
-        G.first = (uint32_t)k;
-        for (const auto &bt : Q.tiles) tl[k++] = bt;
-        G.count = (uint32_t)(k - G.first);
+        // a group of one slot: its record goes in the kernel arguments
+        const auto &T0 = pend[q].tiles.front(), &T1 = pend[q].tiles.back();
+        if (T0.slot == T1.slot) {
+            G.slot = (int32_t)T0.slot;
+            G.tile0 = T0.tile & ~BTILE_TOP;
+        }
         b->groups.push_back(G);
     }
     b->recs.assign(recs, recs + ns);
