@@ -21,9 +21,18 @@ Also reported on the same JSON line:
   roofline_main -- the same quantity for the localized workload (its state
                    is cache resident, so it is latency bound, not HBM bound);
   cpu_baseline  -- the CPU oracle (classical RK4 with its sparse generator)
-                   on a bounded sample of the same workload, one host core.
+                   on a bounded sample of the same workload, one host core;
+  batched       -- 512 independent problems drawn with seed 0 (N, m, L, bath,
+                   coupling and loss drawn over the batched ranges), RK4 steps of
+                   all of them in FP64 and FP32 batches against the plain FP64
+                   propagator called once per problem;
+  serving       -- a Poisson trace of propagation requests (problems as the
+                   batched draw plus a horizon) replayed through the
+                   continuous-batching server and through the plain propagator
+                   one request at a time: solves/s, p50/p99 latency.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+       python bench.py --serve-sweep 0.25,0.5,1,2,10 [--serve-window S] [--serve-deadline S]
 """
 from __future__ import annotations
 
