@@ -137,6 +137,9 @@ def cpu_baseline(p, tier0_amp, dt, budget_s):
                 seconds=round(el, 2), steps=steps)
 
 
+POP_COLS = list(range(1, 9))   # every population of an observable row (cavity ... other sites)
+
+
 def _rate(ms, n_inst, vars_total, steps):
     sec = ms / 1e3
     return {"ms_per_step": round(ms / steps, 4), "instance_steps_per_s": n_inst * steps / sec,
@@ -174,8 +177,11 @@ def batched_section(torch, steps, n=512, seed=0, dt=0.02):
         inst.append((q, T, params, y, work, T.tier0_pure(1.0, 0.0, [0.0] * q.d), info["n_var"]))
     nv = sum(x[6] for x in inst)
     batch = heom.Batch(len(inst))
+    obs_bufs = []
     for i, (q, T, params, y, work, t0v, _) in enumerate(inst):
-        batch.set_slot(i, T, y, work, dt, params=params)
+        T.init_state(t0v, y, st)
+        obs_bufs.append(torch.zeros(3 * 10, dtype=torch.float64, device="cuda"))
+        batch.set_slot(i, T, y, work, dt, params=params, obs=obs_bufs[-1], obs_every=1 + steps)
     batch.commit(torch, st)
     out = {"workload": f"{n} independent problems drawn with seed {seed}: N~U{{4..5000}}, m~U{{1..4}}, "
                        "L~U{3..10}, g~U[0.002,0.03], lam~U[0.005,0.05], gam~U[0.02,0.2], kappa~U[0,0.02], "
@@ -196,6 +202,10 @@ def batched_section(torch, steps, n=512, seed=0, dt=0.02):
         torch.cuda.synchronize()
         out[name] = _rate(e0.elapsed_time(e1), len(inst), nv, steps)
         out[name]["finite"] = bool(all(torch.isfinite(x[3][:64]).all().item() for x in inst[:64]))
+    # every slot recorded its observables after 1 + steps FP64 steps (row 1) and,
+    # from the same start, after 1 + steps FP32 steps (row 2)
+    ob = np.stack([o.cpu().numpy().reshape(-1, 10) for o in obs_bufs])
+    out["max_abs_population_diff_fp32_vs_fp64"] = float(np.abs(ob[:, 2, POP_COLS] - ob[:, 1, POP_COLS]).max())
     del batch
     total_ms = 0.0
     for q, T, params, y, work, t0v, _ in inst:            # plain: one problem at a time
@@ -217,9 +227,6 @@ def batched_section(torch, steps, n=512, seed=0, dt=0.02):
     del inst, imgs
     torch.cuda.empty_cache()
     return out
-
-
-POP_COLS = [1, 2, 4, 5, 6]
 
 
 def serving_point(torch, rate, window, deadline, seed=1, precision=0, budget_gib=256.0,

@@ -361,7 +361,9 @@ class Batch:
         _check(LIB.heom_batch_set_graph(self._h, int(steps)))
 
     def set_merge(self, max_tiles: int):
-        """One launch per stage for batches of at most max_tiles tiles (0 = never)."""
+        """Run the smallest launch groups (m <= 4, at most max_tiles/8 tiles each,
+        max_tiles in all) as one launch per stage (0 = one launch per group).
+        Takes effect at the next commit."""
         _check(LIB.heom_batch_set_merge(self._h, int(max_tiles)))
 
     def slot_steps(self, slot: int) -> int:
