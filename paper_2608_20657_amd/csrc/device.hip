@@ -231,7 +231,7 @@ struct StageArgs {
 enum { BASE_NONE = 0, BASE_IN = 1, BASE_Y = 2 };
 
 // LDS carve-up of one workgroup: tile values, pattern headers, categories,
-// connection records, coefficient tables.
+// connection records, coefficient tables, category multiplicities.
 struct Smem {
     double2 *val;
     double2 *rc;      // grouped sums of the tile's blocks (see process_tile)
@@ -239,6 +239,7 @@ struct Smem {
     CatRec *cat;
     uint32_t *gix;
     double *lut;
+    double *md;       // M_q of the tile's categories as doubles (M_0 resolved per instance)
 };
 
 __device__ __forceinline__ Smem carve(unsigned char *smem, const InstParams &P) {
@@ -249,6 +250,7 @@ __device__ __forceinline__ Smem carve(unsigned char *smem, const InstParams &P) 
     S.cat = reinterpret_cast<CatRec *>(S.hdr + P.max_np);
     S.gix = reinterpret_cast<uint32_t *>(S.cat + P.max_nc);
     S.lut = reinterpret_cast<double *>(S.gix + ((P.max_ng + 3u) & ~3u));
+    S.md = S.lut + 2u * (uint32_t)P.m * (uint32_t)(P.L + 1);
     return S;
 }
 
@@ -334,7 +336,11 @@ __device__ __forceinline__ double2 load_own(const StageArgs &a, uint32_t j) {
 //    block, the thread at position l < 2G+1 forms one of them -- l = 0 the
 //    Z bracket sum_q M_q (X_q - Y_q), l = 1..G the row sum R_{l-1}, l =
 //    G+1..2G the column sum C_{l-1-G} -- into LDS, so the loops over the
-//    block's categories run on a few lanes instead of on every lane.
+//    block's categories run on a few lanes instead of on every lane. Each
+//    sum walks one strided run of the block (column 0, row c+1 or column
+//    c+1) with the multiplicities the threads l = 1..G wrote to LDS as
+//    doubles during the gathers; the excluded diagonal term gets weight 0,
+//    so the loop body has no branches.
 // 4. Every thread reads its Hamiltonian bracket from LDS, adds damping,
 //    loss, the terminator and the extra term, and writes the combination.
 template <int M, bool HAS64, bool HAS32, int BASE, bool EXTRA, bool OUT64, bool TOP>
@@ -395,27 +401,36 @@ __device__ __forceinline__ void process_tile(const InstParams &P, const Dev &D, 
             cfma(hier, make_double2(-dr * P.cci[k], dr * P.ccr[k]), v[3 * M + k]);
         }
     }
+    double *md = S.md + (H.cat_base - TR.c0);
+    if (active && loc - 1u < (uint32_t)G) {   // one thread per category of the block
+        const CatRec cc = cats[loc - 1u];
+        md[loc - 1u] = (cc.flags & CAT_ZERO) ? (P.npool - (double)H.r) : (double)cc.mult;
+    }
     __syncthreads();
 
-    auto mult = [&](int c) -> double {
-        const CatRec cc = cats[c];
-        return (cc.flags & CAT_ZERO) ? (P.npool - (double)H.r) : (double)cc.mult;
-    };
     if (active && loc < (uint32_t)(2 * G + 1)) {
         const bool isZ = loc == 0, isRow = loc <= (uint32_t)G;
         const int c = isZ ? -1 : (isRow ? (int)loc - 1 : (int)loc - 1 - G);
+        // Z: entries (x+1, 0) minus (0, x+1); R_c: (c+1, x+1); C_c: (x+1, c+1)
+        const uint32_t i0 = base + (isZ ? (uint32_t)G1 : (isRow ? (uint32_t)((c + 1) * G1 + 1) : (uint32_t)(G1 + c + 1)));
+        const uint32_t st = (isRow && !isZ) ? 1u : (uint32_t)G1;
         double2 sum = make_double2(0.0, 0.0);
         if (!isZ) {
             sum = S.val[base + (c + 1) * G1 + c + 1];
             if ((H.tmask >> c) & 1u)
-                sum = cadd(sum, cscale(mult(c) - 1.0, S.val[base + nm + __popc(H.tmask & ((1u << c) - 1u))]));
+                sum = cadd(sum, cscale(md[c] - 1.0, S.val[base + nm + __popc(H.tmask & ((1u << c) - 1u))]));
         }
+        // branch-free body: the Y_x term is read by every lane and weighted
+        // by zf (1 for the Z bracket, else 0); the diagonal's weight is
+        // masked to +0 with integer ops, so no load is predicated
+        const double zf = isZ ? 1.0 : 0.0;
+#pragma unroll 2
         for (int x = 0; x < G; ++x) {
-            if (x == c) continue;
-            const int ia = isZ ? (x + 1) * G1 : (isRow ? (c + 1) * G1 + x + 1 : (x + 1) * G1 + c + 1);
-            double2 w = S.val[base + ia];
-            if (isZ) w = csub(w, S.val[base + x + 1]);
-            sum = cadd(sum, cscale(mult(x), w));
+            const double2 w1 = S.val[i0 + (uint32_t)x * st], w2 = S.val[base + 1u + (uint32_t)x];
+            const unsigned long long keep = x == c ? 0ull : ~0ull;
+            const double mx = __longlong_as_double((long long)((unsigned long long)__double_as_longlong(md[x]) & keep));
+            const double2 w = make_double2(w1.x - zf * w2.x, w1.y - zf * w2.y);
+            sum = cadd(sum, cscale(mx, w));
         }
         S.rc[base + loc] = sum;
     }

@@ -548,9 +548,9 @@ int make_tiles(HostTables *t, int tile_vars, std::string *err) {
     for (size_t k = 0; k < t->tiles.size(); ++k)
         if (t->hdr[t->tiles[k].p0].tier == t->L) { t->top_tile = (uint32_t)k; break; }
     // LDS per workgroup: values, grouped sums, pattern headers, categories,
-    // gather indices, coefficient tables
+    // gather indices, coefficient tables, category multiplicities (FP64)
     t->lds_bytes = 32u * tile_vars + 32u * t->max_np + 16u * t->max_nc + 4u * ((t->max_ng + 3u) & ~3u) +
-                   16u * (uint32_t)t->m * (uint32_t)(t->L + 1);
+                   16u * (uint32_t)t->m * (uint32_t)(t->L + 1) + 8u * t->max_nc;
     if (t->lds_bytes > 64u * 1024u) {
         *err = "tile needs more than 64 KiB of LDS";
         return HEOM_E_UNSUPPORTED;
