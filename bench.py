@@ -88,7 +88,7 @@ def run_solve(T, torch, tier0, dt, steps, obs_every, precision):
     info = T.info()
     s = torch.cuda.current_stream()
     y = torch.empty(info["n_var"], dtype=torch.complex128, device="cuda")
-    wb = info["work_bytes_fp64"] if precision == 0 else info["work_bytes_fp32"]
+    wb = info["work_bytes_fp64"] if (precision & 1) == 0 else info["work_bytes_fp32"]
     work = torch.empty(wb, dtype=torch.uint8, device="cuda")
     nobs = steps // obs_every + 1 if obs_every else 1
     obs = torch.zeros(nobs * 10, dtype=torch.float64, device="cuda")
@@ -146,7 +146,7 @@ def _rate(ms, n_inst, vars_total, steps):
             "rhs_updates_per_s": vars_total * 4 * steps / sec}
 
 
-def batched_section(torch, steps, n=512, seed=0, dt=0.02):
+def batched_section(torch, steps, n=512, seed=0, dt=0.02, flag=0):
     """Many independent problems at once: the batched launch (every instance
     in one launch per stage and per m) in FP64 and FP32-bulk, against the
     plain per-instance FP64 propagator called once per instance. Time per
@@ -193,11 +193,11 @@ def batched_section(torch, steps, n=512, seed=0, dt=0.02):
     for prec, name in ((0, "fp64_batched"), (1, "fp32_batched")):
         for q, T, params, y, work, t0v, _ in inst:
             T.init_state(t0v, y, st)
-        batch.propagate(1, prec, st)                       # warm-up step
+        batch.propagate(1, prec | flag, st)                # warm-up step
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record(st)
-        batch.propagate(steps, prec, st)
+        batch.propagate(steps, prec | flag, st)
         e1.record(st)
         torch.cuda.synchronize()
         out[name] = _rate(e0.elapsed_time(e1), len(inst), nv, steps)
@@ -212,11 +212,11 @@ def batched_section(torch, steps, n=512, seed=0, dt=0.02):
         T.set_params(q)
         T.upload(imgs[S.structure_key(q)], st)
         T.init_state(t0v, y, st)
-        T.propagate(y, work, dt, 1, 0, None, 0, st)        # warm-up step
+        T.propagate(y, work, dt, 1, 0, None, flag, st)     # warm-up step
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record(st)
-        T.propagate(y, work, dt, steps, 0, None, 0, st)
+        T.propagate(y, work, dt, steps, 0, None, flag, st)
         e1.record(st)
         torch.cuda.synchronize()
         total_ms += e0.elapsed_time(e1)

@@ -59,6 +59,7 @@ extern "C" {
 
 #define HEOM_FP64    0     /* precision: complex FP64 throughout */
 #define HEOM_FP32    1     /* precision: complex FP32 RK4 increments, FP64 state */
+#define HEOM_HERMITIAN 2   /* flag OR-ed into precision: every ADO is Hermitian (see heom_propagate) */
 
 /* One problem (Sec. II, Eqs. HS, BCF-exp, scaled-HEOM; Sec. VI.B for d).
  * Units are the caller's, with hbar = 1. */
@@ -93,6 +94,9 @@ typedef struct heom_sizes {
     int32_t max_G;           /* largest category count */
     int32_t tile_vars;       /* variables per tile (workgroup size) */
     int64_t hier_gathers;    /* hierarchy reads of one right-hand side */
+    int64_t rhs_work_bytes;  /* device work bytes heom_rhs needs (0 without transposed copies) */
+    int32_t transposed;      /* 1 if the kernels keep transposed copies (see heom_tuning) */
+    int32_t reserved;
 } heom_sizes;
 
 /* Build the pattern list, unique-variable layout and connection tables of
@@ -164,8 +168,11 @@ int heom_init_state(const heom_tables *t, const double *tier0, void *y_dev, void
  * (Eq. Gamma-Lambda-one and its m-channel form), cavity loss, the terminator
  * if set, and the hierarchy couplings read through the connection records
  * (Eqs. uvar-up, uvar-down). y_dev and dy_dev: n_var complex128, distinct.
- * Requires heom_upload. */
-int heom_rhs(const heom_tables *t, const void *y_dev, void *dy_dev, void *stream);
+ * work_dev: rhs_work_bytes of device scratch (the transposed copy of y when
+ * the tables keep transposed copies; may be NULL when rhs_work_bytes is 0).
+ * Requires heom_upload. Errors: E_TOO_LARGE if work_bytes is too small. */
+int heom_rhs(const heom_tables *t, const void *y_dev, void *dy_dev, void *work_dev, size_t work_bytes,
+             void *stream);
 
 /* Propagate y_dev in place by nsteps classical RK4 steps of size dt (the
  * integrator of Sec. VII.C). The linear generator is autonomous, so a step
@@ -173,7 +180,8 @@ int heom_rhs(const heom_tables *t, const void *y_dev, void *dy_dev, void *stream
  * degree-4 polynomial in hM as the k1..k4 form, with four fused
  * right-hand-side + combination stages.
  *   precision HEOM_FP64: all stages in complex FP64; work_dev holds
- *     work_bytes_fp64 bytes (two state vectors).
+ *     work_bytes_fp64 bytes (two state vectors, and with transposed copies
+ *     (heom_tuning) three more: the copies of y and of the two).
  *   precision HEOM_FP32: y stays complex FP64; the increments
  *     u1 = h/4 M y, u2 = h/3 M (y + u1), u3 = h/2 M (y + u2) are stored as
  *     complex FP32, and each later stage gathers only its FP32 increment,
@@ -181,6 +189,15 @@ int heom_rhs(const heom_tables *t, const void *y_dev, void *dy_dev, void *stream
  *     place. Multiplicities, square-root weights, damping, the arithmetic
  *     and the combination with y stay FP64; work_dev holds work_bytes_fp32
  *     bytes.
+ * precision | HEOM_HERMITIAN: the caller asserts that every ADO of y is
+ *   Hermitian (rho_n^dagger = rho_n: a Hermitian rho_S(0) propagated with
+ *   c_check = conj(c), Eq. adjoint-preservation), so that the entry a
+ *   column-molecule move needs is the complex conjugate of the entry with
+ *   row and column exchanged. Tables with transposed copies (heom_tuning)
+ *   then read that mirrored entry of y's own row-major layout and keep no
+ *   copies; other tables ignore the flag. Results agree with the general
+ *   path to rounding (the two mirrored entries are computed by different
+ *   threads), not bitwise. Errors: E_INVAL if c_check != conj(c).
  * If obs_every > 0, obs_dev (device, (nsteps/obs_every + 1)*HEOM_NOBS
  * doubles) receives the observables of heom_observables before the first
  * step and after every obs_every steps. obs_dev may be NULL if obs_every is 0.
@@ -229,10 +246,18 @@ typedef struct heom_tuning {
     int32_t spin_limit;      /* polls before a grid barrier gives up (0 = default, about 4 s) */
     int32_t cache_policy;    /* streaming (non-temporal) hints: bit 0 own-value loads, bit 1 loads of
                                 the RK4 base vector, bit 2 stores (default 6) */
+    int32_t transposed;      /* transposed copies: 1 on, 0 off, -1 (default) on for states of
+                                2^19 or more variables. With copies on, every stage also writes its
+                                output with each block's category matrix transposed, and the
+                                column-molecule moves (Eqs. uvar-up, uvar-down, column terms) gather
+                                from that copy, where the entries one column move reads are
+                                contiguous; work_bytes grow from 32 to 80 bytes per variable and the
+                                persistent launch is not used. */
 } heom_tuning;
 
-/* Set or read the launch configuration. A new tile_vars rebuilds the tiles
- * and needs a new heom_upload (table_bytes may change). Results do not
+/* Set or read the launch configuration. A new tile_vars or a change of the
+ * effective `transposed` rebuilds the tiles and needs a new heom_upload
+ * (table_bytes and the work sizes may change). Results do not
  * depend on the configuration (every variable has one writer, and the sum
  * order inside a variable is fixed). Errors: E_INVAL if tile_vars is not
  * allowed or smaller than the largest pattern block. */
@@ -294,14 +319,18 @@ int heom_batch_device_bytes(const heom_batch *b, size_t *bytes);
 /* Upload the slot records and the tile list (grouped by m) into caller
  * device memory (256-byte aligned, >= heom_batch_device_bytes), and write
  * observable sample 0 of every slot that has not stepped yet, synchronously
- * on `stream`. Required after any set/clear. */
+ * on `stream`. Required after any set/clear, and after re-tuning a slot's
+ * tables. Errors: E_STATE if a slot's tables are not uploaded, E_TOO_LARGE
+ * if a slot's work buffer is smaller than its tables' work_bytes now. */
 int heom_batch_commit(heom_batch *b, void *dev, size_t bytes, void *stream);
 
 /* Advance every occupied slot by nsteps RK4 steps of its own dt (the same
  * fused stages as heom_propagate; one launch per stage and per m covers the
- * tiles of all slots). Each problem's trajectory is bitwise the same as with
+ * tiles of all slots; slots whose tables keep transposed copies get the copy
+ * of y made at the start of each call). Each problem's trajectory is bitwise the same as with
  * heom_propagate alone (no slot reads another slot's memory). precision as
- * in heom_propagate. Errors: E_STATE if not committed since the last change. */
+ * in heom_propagate, HEOM_HERMITIAN included (not checked against the slots'
+ * parameter blocks here: the caller asserts it for every slot). Errors: E_STATE if not committed since the last change. */
 int heom_batch_propagate(heom_batch *b, int64_t nsteps, int precision, void *stream);
 
 /* Replay whole groups of `steps` RK4 steps from a HIP graph captured on the

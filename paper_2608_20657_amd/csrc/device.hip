@@ -29,6 +29,7 @@ struct BatchSlotHost {
     const heom_tables *tables = nullptr;
     const void *params = nullptr;
     void *y = nullptr, *work = nullptr;
+    size_t work_bytes = 0;
     double dt = 0.0;
     double *obs = nullptr;
     int64_t obs_every = 0, obs_cap = 0, steps = 0;
@@ -50,6 +51,8 @@ struct SlotRec {
     const double *lut;
     double2 *y, *w0, *w1;     // FP64 stage vectors
     float2 *u1, *u2, *u3;     // FP32 increments
+    double2 *yT, *w0T, *w1T;  // transposed copies (null without them)
+    float2 *u1T, *u2T, *u3T;
     double *obs;
     int64_t obs_every, obs_cap, step0;
     double dt;
@@ -214,9 +217,16 @@ __device__ __forceinline__ void st_stream(float2 *p, double2 v) {
 // Vectors one stage reads and writes:
 //   out[i] = base(i) + alpha * ((M_u in)[i] + extra_scale * extra[i])
 // with in = in64 (+ in32), base = in (BASE 1) or ybase (BASE 2) or 0.
+// With transposed copies, inT64 / inT32 hold `in` with every block's
+// category matrix transposed (column moves gather there) and outT64 /
+// outT32, if set, receive `out` in the same form; a null inT means `in`.
 struct StageArgs {
     const double2 *in64;
     const float2 *in32;
+    const double2 *inT64;
+    const float2 *inT32;
+    double2 *outT64;
+    float2 *outT32;
     const double2 *ybase;
     const float2 *extra;
     double extra_scale;
@@ -224,7 +234,8 @@ struct StageArgs {
     float2 *out32;
     double alpha;
     double *obs;          // observables of the tier-0 block after this stage
-    uint32_t policy;      // bit 0: non-temporal own-value loads, 1: y loads, 2: stores
+    uint32_t policy;      // bit 0: non-temporal own-value loads, 1: y loads, 2: stores;
+                          // bit 3: mirrored column gathers (see load_col)
     uint32_t tile0;       // first tile of this launch
 };
 
@@ -372,33 +383,67 @@ __device__ __forceinline__ void process_tile(const InstParams &P, const Dev &D, 
     if (active) {
         const CatRec cq = A > 0 ? cats[A - 1] : CatRec{}, cr2 = B > 0 ? cats[B - 1] : CatRec{};
         uint32_t idx[4 * M];
-        double2 v[4 * M];
+        double2 v[4 * M];   // FP64 gathers
+        float2 f[4 * M];    // FP32 gathers, widened where they are used
 #pragma unroll
         for (int j = 0; j < 4 * M; ++j) {
             const bool up_slot = ((j / M) & 1) == 0;   // slots 0..M-1 and 2M..3M-1 are up moves
             idx[j] = (!(TOP && up_slot) && ((live >> j) & 1u)) ? S.gix[goff + __popc(live & ((1u << j) - 1u))] : 0u;
         }
+        // Column-move gathers (slots 2M..4M-1) read the transposed copy when
+        // there is one. With policy bit 3 the ADOs are Hermitian
+        // (rho_n^dagger = rho_n): the entry with row and column exchanged,
+        // read from `in` itself at the position the transposed copy would
+        // have, is the complex conjugate of the one needed; it is conjugated
+        // where it is used. Nothing is done to a value between its load and
+        // its use, so the loads of all slots go out as one batch.
+        const bool mirror = (a.policy & 8u) != 0;
+        const double2 *c64 = (mirror || !a.inT64) ? a.in64 : a.inT64;
+        const float2 *c32 = (mirror || !a.inT32) ? a.in32 : a.inT32;
+        // +0.0f that the compiler cannot see as a constant (policy < 2^16):
+        // with a constant for the dead slots it moves each widening into the
+        // load's branch, which then waits for that load alone
+        const float fz = __int_as_float((int)(a.policy >> 16));
 #pragma unroll
         for (int j = 0; j < 4 * M; ++j) {
             const bool up_slot = ((j / M) & 1) == 0;
-            v[j] = (!(TOP && up_slot) && ((live >> j) & 1u)) ? load_in<HAS64, HAS32>(a, idx[j]) : make_double2(0.0, 0.0);
+            const bool colmv = j >= 2 * M;
+            v[j] = make_double2(0.0, 0.0);
+            f[j] = make_float2(fz, fz);
+            if (!(TOP && up_slot) && ((live >> j) & 1u)) {
+                if (HAS64) v[j] = (colmv ? c64 : a.in64)[idx[j]];
+                if (HAS32) f[j] = (colmv ? c32 : a.in32)[idx[j]];
+            }
         }
+        auto gv = [&](int j) -> double2 {
+            double2 r = v[j];
+            if (HAS32) {
+                r.x += (double)f[j].x;
+                r.y += (double)f[j].y;
+            }
+            return r;
+        };
         S.val[t] = own;
         // row moves -i sqrt((n+1)|c|), -i sqrt(n/|c|) c_k (P: c_k - cc_k);
         // column moves +i sqrt((n+1)|c|), +i sqrt(n/|c|) cc_k
         const int L1 = P.L + 1;
         const double *up = S.lut;
         const double *dn = S.lut + M * L1;
+        const double cs = (a.policy & 8u) ? -1.0 : 1.0;   // mirrored column gathers: conjugate
 #pragma unroll
         for (int k = 0; k < M; ++k) {
             const uint32_t nq = vbyte(cq.vec, k), nr = vbyte(cr2.vec, k);
             const double dq = dn[k * L1 + nq], dr = dn[k * L1 + nr];
             const double cre = kind == KIND_P ? P.cr[k] - P.ccr[k] : P.cr[k];
             const double cim = kind == KIND_P ? P.ci[k] - P.cci[k] : P.ci[k];
-            if (!TOP) cfma(hier, make_double2(0.0, -up[k * L1 + nq]), v[k]);
-            cfma(hier, make_double2(dq * cim, -dq * cre), v[M + k]);
-            if (!TOP) cfma(hier, make_double2(0.0, up[k * L1 + nr]), v[2 * M + k]);
-            cfma(hier, make_double2(-dr * P.cci[k], dr * P.ccr[k]), v[3 * M + k]);
+            if (!TOP) cfma(hier, make_double2(0.0, -up[k * L1 + nq]), gv(k));
+            cfma(hier, make_double2(dq * cim, -dq * cre), gv(M + k));
+            if (!TOP) {
+                const double2 w = gv(2 * M + k);
+                cfma(hier, make_double2(0.0, up[k * L1 + nr]), make_double2(w.x, cs * w.y));
+            }
+            const double2 w = gv(3 * M + k);
+            cfma(hier, make_double2(-dr * P.cci[k], dr * P.ccr[k]), make_double2(w.x, cs * w.y));
         }
     }
     double *md = S.md + (H.cat_base - TR.c0);
@@ -476,6 +521,17 @@ __device__ __forceinline__ void process_tile(const InstParams &P, const Dev &D, 
         } else {
             if (OUT64) a.out64[TR.v0 + t] = res;
             else a.out32[TR.v0 + t] = make_float2((float)res.x, (float)res.y);
+        }
+        if (OUT64 ? a.outT64 != nullptr : a.outT32 != nullptr) {
+            // position of this entry in the transposed copy (T_q in place)
+            const uint32_t tp = TR.v0 + (isT ? t : base + B * (uint32_t)G1 + A);
+            if (a.policy & 4u) {
+                if (OUT64) st_stream(a.outT64 + tp, res);
+                else st_stream(a.outT32 + tp, res);
+            } else {
+                if (OUT64) a.outT64[tp] = res;
+                else a.outT32[tp] = make_float2((float)res.x, (float)res.y);
+            }
         }
     }
     __syncthreads();
@@ -668,6 +724,12 @@ __device__ __forceinline__ BatchCtx batch_ctx(const SlotRec &rec, uint32_t tile,
     R.u1 = as_global(R.u1);
     R.u2 = as_global(R.u2);
     R.u3 = as_global(R.u3);
+    R.yT = as_global(R.yT);
+    R.w0T = as_global(R.w0T);
+    R.w1T = as_global(R.w1T);
+    R.u1T = as_global(R.u1T);
+    R.u2T = as_global(R.u2T);
+    R.u3T = as_global(R.u3T);
     R.obs = as_global(R.obs);
     const InstParams &P = *reinterpret_cast<const InstParams *>(R.params);
     Dev &D = c.D;
@@ -688,23 +750,33 @@ __device__ __forceinline__ BatchCtx batch_ctx(const SlotRec &rec, uint32_t tile,
     const int64_t gst = s == 3 ? R.step0 + *as_global(ctr) : 0;
     StageArgs &a = c.a;
     a = StageArgs{};
-    a.policy = policy;
+    // mirrored column gathers need transposed tables (R.yT is set exactly
+    // then); with them, the slot neither reads nor writes copies
+    const bool trcol = R.yT != nullptr, mirror = (policy & 8u) && trcol;
+    a.policy = mirror ? policy : (policy & ~8u);
+    if (mirror) R.yT = R.w0T = R.w1T = nullptr, R.u1T = R.u2T = R.u3T = nullptr;
     a.alpha = s == 0 ? h / 4.0 : (s == 1 ? h / 3.0 : (s == 2 ? h / 2.0 : h));
     a.obs = (s == 3 && R.obs != nullptr && R.obs_every > 0 && gst % R.obs_every == 0 && gst / R.obs_every < R.obs_cap)
                 ? R.obs + (gst / R.obs_every) * HEOM_NOBS : nullptr;
     c.first = tile == 0;
     if (PREC == HEOM_FP64) {
         a.in64 = s == 0 ? R.y : (s == 2 ? R.w1 : R.w0);
+        a.inT64 = s == 0 ? R.yT : (s == 2 ? R.w1T : R.w0T);
         a.ybase = R.y;
         a.out64 = s == 3 ? R.y : (s == 1 ? R.w1 : R.w0);
+        a.outT64 = s == 3 ? R.yT : (s == 1 ? R.w1T : R.w0T);
     } else {
         a.in64 = R.y;
+        a.inT64 = R.yT;
         a.in32 = s == 1 ? R.u1 : (s == 2 ? R.u2 : R.u3);
+        a.inT32 = s == 1 ? R.u1T : (s == 2 ? R.u2T : R.u3T);
         a.extra = R.u1;
         a.extra_scale = 4.0 / h;
         a.ybase = R.y;
         a.out32 = s == 0 ? R.u1 : (s == 1 ? R.u2 : R.u3);
+        a.outT32 = s == 0 ? R.u1T : (s == 1 ? R.u2T : R.u3T);
         a.out64 = R.y;
+        a.outT64 = R.yT;
     }
     return c;
 }
@@ -801,6 +873,21 @@ __global__ void zero_kernel(double2 *y, uint32_t n) {
         y[i] = make_double2(0.0, 0.0);
 }
 
+// yT = y with every block's category matrix transposed (T_q in place); one
+// workgroup per tile, one thread per variable.
+__global__ void transpose_kernel(const TileRec *tiles, const VarRec *vrec, const PatHdr *hdr, const double2 *y,
+                                 double2 *yT) {
+    const TileRec TR = tiles[blockIdx.x];
+    const uint32_t t = threadIdx.x;
+    if (t >= TR.nv) return;
+    const VarRec vr = vrec[TR.v0 + t];
+    const uint32_t p = vr.x & 127u, A = (vr.x >> 7) & 31u, B = (vr.x >> 12) & 31u;
+    const bool isT = (vr.x >> 17) & 1u;
+    const PatHdr H = hdr[TR.p0 + p];
+    const uint32_t base = H.off - TR.v0, G1 = (uint32_t)H.G + 1u;
+    yT[TR.v0 + (isT ? t : base + B * G1 + A)] = y[TR.v0 + t];
+}
+
 // States of at least this many tiles run their top tier as a second launch
 // with the kernel variant that has no up moves (fewer registers, more waves);
 // for smaller ones the extra launch costs more than it saves.
@@ -808,7 +895,7 @@ constexpr uint32_t TOP_SPLIT_TILES = 2048;
 
 template <int M, bool HAS64, bool HAS32, int BASE, bool EXTRA, bool OUT64>
 void launch_m(const HostTables &t, hipStream_t s, StageArgs a) {
-    a.policy = (uint32_t)t.tune.cache_policy;
+    a.policy = (uint32_t)t.tune.cache_policy | (a.policy & 8u);
     const uint32_t T = (uint32_t)t.tiles.size();
     // Large states: the top tier (no up moves) runs in its own launch with a
     // kernel that has no up-move slots, fewer registers and more waves.
@@ -847,6 +934,47 @@ __global__ void zero_u32_kernel(uint32_t *p, uint32_t n) {
 constexpr uint32_t MAX_PERSIST_WG = 2048;
 constexpr size_t CTRL_BYTES = 256 + 64 * (size_t)MAX_PERSIST_WG;
 
+// Work buffer: the stage vectors (32 bytes per variable; 80 with transposed
+// copies), then the control area.
+//   FP64: w0 [0, 16n), w1 [16n, 32n); copies yT [32n, 48n), w0T [48n, 64n),
+//         w1T [64n, 80n)
+//   FP32: u3 [0, 8n), u1 [16n, 24n), u2 [24n, 32n); copies yT [32n, 48n),
+//         u1T [48n, 56n), u2T [56n, 64n), u3T [64n, 72n)
+struct WorkView {
+    double2 *w0, *w1, *yT, *w0T, *w1T;
+    float2 *u1, *u2, *u3, *u1T, *u2T, *u3T;
+    unsigned char *ctrl;
+};
+size_t vec_bytes(const HostTables &t) { return (size_t)t.n_var * (t.trcol ? 80 : 32); }
+WorkView work_view(const HostTables &t, void *work) {
+    const size_t n = t.n_var;
+    unsigned char *wb = static_cast<unsigned char *>(work);
+    WorkView w{};
+    w.w0 = reinterpret_cast<double2 *>(wb);
+    w.w1 = w.w0 + n;
+    w.u3 = reinterpret_cast<float2 *>(wb);
+    w.u1 = reinterpret_cast<float2 *>(wb + 16 * n);
+    w.u2 = w.u1 + n;
+    if (t.trcol) {
+        w.yT = reinterpret_cast<double2 *>(wb + 32 * n);
+        w.w0T = w.yT + n;
+        w.w1T = w.w0T + n;
+        w.u1T = reinterpret_cast<float2 *>(wb + 48 * n);
+        w.u2T = w.u1T + n;
+        w.u3T = w.u2T + n;
+    }
+    w.ctrl = wb + vec_bytes(t);
+    return w;
+}
+
+int launch_transpose(const HostTables &t, hipStream_t s, const double2 *y, double2 *yT) {
+    const Dev D = dev_view(t);
+    hipLaunchKernelGGL(transpose_kernel, dim3((uint32_t)t.tiles.size()), dim3(t.tile_vars), 0, s, D.tiles, D.vrec,
+                       D.hdr, y, yT);
+    HIP_TRY(hipGetLastError());
+    return HEOM_OK;
+}
+
 template <int M, int PREC>
 int launch_persistent_m(const HostTables &t, hipStream_t s, PersistArgs pa, bool *used) {
     auto kern = persistent_kernel<M, PREC>;
@@ -877,6 +1005,7 @@ int launch_persistent_m(const HostTables &t, hipStream_t s, PersistArgs pa, bool
 }
 
 int launch_persistent(const HostTables &t, hipStream_t s, const PersistArgs &pa, int prec, bool *used) {
+    if (t.trcol) { *used = false; return HEOM_OK; }   // the persistent kernel keeps no transposed copies
 #define HEOM_PCASE(MM) \
     case MM: return prec == HEOM_FP64 ? launch_persistent_m<MM, HEOM_FP64>(t, s, pa, used) \
                                       : launch_persistent_m<MM, HEOM_FP32>(t, s, pa, used);
@@ -888,7 +1017,16 @@ int launch_persistent(const HostTables &t, hipStream_t s, const PersistArgs &pa,
 #undef HEOM_PCASE
 }
 
-size_t work_bytes_for(const HostTables &t) { return (size_t)t.n_var * 32 + CTRL_BYTES; }
+size_t work_bytes_for(const HostTables &t) { return vec_bytes(t) + CTRL_BYTES; }
+size_t rhs_work_bytes_for(const HostTables &t) { return t.trcol ? (size_t)t.n_var * 16 : 0; }
+
+// c_check_k = conj(c_k) for every channel: the condition under which the
+// propagation maps Hermitian ADOs to Hermitian ADOs (Eq. adjoint-preservation).
+bool adjoint_preserving(const HostTables &t) {
+    for (int k = 0; k < t.m; ++k)
+        if (t.cc[2 * k] != t.c[2 * k] || t.cc[2 * k + 1] != -t.c[2 * k + 1]) return false;
+    return true;
+}
 
 int check_ready(const heom_tables *h) {
     if (!h) return fail(HEOM_E_INVAL, "tables handle is NULL");
@@ -974,7 +1112,9 @@ int batch_launch(const heom_batch *b, hipStream_t s, int stage, uint32_t policy)
 
 // One RK4 step of every slot: four stage launches per group.
 int batch_step(const heom_batch *b, hipStream_t s, int precision) {
-    const uint32_t policy = 6u;
+    // bit 3: Hermitian ADOs (slots with transposed tables read mirrored entries)
+    const uint32_t policy = 6u | ((precision & HEOM_HERMITIAN) ? 8u : 0u);
+    precision &= ~HEOM_HERMITIAN;
     for (int stage = 0; stage < 4; ++stage) {
         const int rc = precision == HEOM_FP64 ? batch_launch<HEOM_FP64>(b, s, stage, policy)
                                               : batch_launch<HEOM_FP32>(b, s, stage, policy);
@@ -1068,6 +1208,9 @@ int heom_table_info(const heom_tables *h, heom_sizes *out) {
     out->max_G = t.max_G;
     out->tile_vars = t.tile_vars;
     out->hier_gathers = t.hier_gathers;
+    out->rhs_work_bytes = (int64_t)rhs_work_bytes_for(t);
+    out->transposed = t.trcol ? 1 : 0;
+    out->reserved = 0;
     return HEOM_OK;
 }
 
@@ -1187,16 +1330,28 @@ int heom_init_state(const heom_tables *h, const double *tier0, void *y_dev, void
     return HEOM_OK;
 }
 
-int heom_rhs(const heom_tables *h, const void *y_dev, void *dy_dev, void *stream) {
+int heom_rhs(const heom_tables *h, const void *y_dev, void *dy_dev, void *work_dev, size_t work_bytes,
+             void *stream) {
     if (int rc = check_ready(h)) return rc;
     if (int rc = check_dev(y_dev, "y_dev")) return rc;
     if (int rc = check_dev(dy_dev, "dy_dev")) return rc;
     if (y_dev == dy_dev) return fail(HEOM_E_INVAL, "y_dev and dy_dev must differ");
+    const HostTables &t = h->t;
+    const size_t need = rhs_work_bytes_for(t);
+    if (need > 0 && !work_dev) return fail(HEOM_E_INVAL, "work_dev is NULL");
+    if (work_bytes < need) return fail(HEOM_E_TOO_LARGE, "work buffer smaller than rhs_work_bytes");
+    hipStream_t s = static_cast<hipStream_t>(stream);
     StageArgs a{};
     a.in64 = static_cast<const double2 *>(y_dev);
     a.out64 = static_cast<double2 *>(dy_dev);
     a.alpha = 1.0;
-    return launch_stage<true, false, BASE_NONE, false, true>(h->t, static_cast<hipStream_t>(stream), a);
+    if (t.trcol) {
+        double2 *yT = static_cast<double2 *>(work_dev);
+        if (work_dev == y_dev || work_dev == dy_dev) return fail(HEOM_E_INVAL, "work_dev overlaps y_dev or dy_dev");
+        if (int rc = launch_transpose(t, s, a.in64, yT)) return rc;
+        a.inT64 = yT;
+    }
+    return launch_stage<true, false, BASE_NONE, false, true>(t, s, a);
 }
 
 int heom_observables(const heom_tables *h, const void *y_dev, double *obs_dev, void *stream) {
@@ -1217,10 +1372,13 @@ int heom_propagate(const heom_tables *h, void *y_dev, void *work_dev, size_t wor
     if (int rc = check_dev(work_dev, "work_dev")) return rc;
     if (!(std::isfinite(dt)) || nsteps < 0 || obs_every < 0) return fail(HEOM_E_INVAL, "bad dt, nsteps or obs_every");
     if (obs_every > 0 && !obs_dev) return fail(HEOM_E_INVAL, "obs_dev is NULL");
+    const bool hermitian = (precision & HEOM_HERMITIAN) != 0;
+    precision &= ~HEOM_HERMITIAN;
     if (precision != HEOM_FP64 && precision != HEOM_FP32) return fail(HEOM_E_INVAL, "unknown precision");
     const HostTables &t = h->t;
-    const size_t n = t.n_var;
     if (work_bytes < work_bytes_for(t)) return fail(HEOM_E_TOO_LARGE, "work buffer smaller than work_bytes");
+    if (hermitian && !adjoint_preserving(t))
+        return fail(HEOM_E_INVAL, "HEOM_HERMITIAN needs c_check = conj(c) for every channel");
     hipStream_t s = static_cast<hipStream_t>(stream);
     double2 *y = static_cast<double2 *>(y_dev);
     if (obs_every > 0) {
@@ -1228,7 +1386,7 @@ int heom_propagate(const heom_tables *h, void *y_dev, void *work_dev, size_t wor
         HIP_TRY(hipGetLastError());
     }
     if (nsteps == 0) return HEOM_OK;
-    unsigned char *wb = static_cast<unsigned char *>(work_dev);
+    const WorkView wv = work_view(t, work_dev);
     PersistArgs pa{};
     pa.y = y;
     pa.dt = dt;
@@ -1236,17 +1394,17 @@ int heom_propagate(const heom_tables *h, void *y_dev, void *work_dev, size_t wor
     pa.nsteps = nsteps;
     pa.obs_every = obs_every;
     pa.obs = obs_every > 0 ? obs_dev : nullptr;
-    pa.timeout = reinterpret_cast<uint32_t *>(wb + 32 * n + 4);
-    pa.flags = reinterpret_cast<uint32_t *>(wb + 32 * n + 256);
+    pa.timeout = reinterpret_cast<uint32_t *>(wv.ctrl + 4);
+    pa.flags = reinterpret_cast<uint32_t *>(wv.ctrl + 256);
     pa.limit = t.tune.spin_limit > 0 ? (uint32_t)t.tune.spin_limit : (1u << 20);
     pa.policy = (uint32_t)t.tune.cache_policy;
     if (precision == HEOM_FP64) {
-        pa.w0 = reinterpret_cast<double2 *>(wb);
-        pa.w1 = pa.w0 + n;
+        pa.w0 = wv.w0;
+        pa.w1 = wv.w1;
     } else {
-        pa.u3 = reinterpret_cast<float2 *>(wb);
-        pa.u1 = reinterpret_cast<float2 *>(wb + 16 * n);
-        pa.u2 = pa.u1 + n;
+        pa.u3 = wv.u3;
+        pa.u1 = wv.u1;
+        pa.u2 = wv.u2;
     }
     hipLaunchKernelGGL(zero_u32_kernel, dim3(64), dim3(256), 0, s, pa.timeout - 1, (uint32_t)(CTRL_BYTES / 4));
     HIP_TRY(hipGetLastError());
@@ -1256,21 +1414,33 @@ int heom_propagate(const heom_tables *h, void *y_dev, void *work_dev, size_t wor
         if (int rc = launch_persistent(t, s, pa, precision, &used)) return rc;
         if (used) return HEOM_OK;
     }
-    // one launch per stage
+    // one launch per stage; with transposed copies, y's copy is made once
+    // here and each stage then writes the copy of its own output. Hermitian
+    // ADOs need no copies: column gathers read the mirrored entry.
     const double h1 = dt / 4.0, h2 = dt / 3.0, h3 = dt / 2.0, h4 = dt;
     int rc;
+    const bool mirror = hermitian && t.trcol;
+    WorkView cv = wv;                       // the copies, or none
+    if (mirror) cv.yT = cv.w0T = cv.w1T = nullptr, cv.u1T = cv.u2T = cv.u3T = nullptr;
+    const uint32_t pol = mirror ? 8u : 0u;
+    if (t.trcol && !mirror && (rc = launch_transpose(t, s, y, wv.yT))) return rc;
     if (precision == HEOM_FP64) {
-        double2 *wa = pa.w0, *wbv = pa.w1;
+        double2 *wa = pa.w0, *wbv = pa.w1, *waT = cv.w0T, *wbT = cv.w1T;
         for (int64_t st = 1; st <= nsteps; ++st) {
             double *ob = (obs_every > 0 && st % obs_every == 0) ? obs_dev + (st / obs_every) * HEOM_NOBS : nullptr;
             StageArgs a{};
-            a.in64 = y; a.out64 = wa; a.alpha = h1;
+            a.policy = pol;
+            a.in64 = y; a.inT64 = cv.yT; a.out64 = wa; a.outT64 = waT; a.alpha = h1;
             if ((rc = launch_stage<true, false, BASE_IN, false, true>(t, s, a))) return rc;
-            a = StageArgs{}; a.in64 = wa; a.ybase = y; a.out64 = wbv; a.alpha = h2;
+            a = StageArgs{}; a.policy = pol;
+            a.in64 = wa; a.inT64 = waT; a.ybase = y; a.out64 = wbv; a.outT64 = wbT; a.alpha = h2;
             if ((rc = launch_stage<true, false, BASE_Y, false, true>(t, s, a))) return rc;
-            a = StageArgs{}; a.in64 = wbv; a.ybase = y; a.out64 = wa; a.alpha = h3;
+            a = StageArgs{}; a.policy = pol;
+            a.in64 = wbv; a.inT64 = wbT; a.ybase = y; a.out64 = wa; a.outT64 = waT; a.alpha = h3;
             if ((rc = launch_stage<true, false, BASE_Y, false, true>(t, s, a))) return rc;
-            a = StageArgs{}; a.in64 = wa; a.ybase = y; a.out64 = y; a.alpha = h4; a.obs = ob;
+            a = StageArgs{}; a.policy = pol;
+            a.in64 = wa; a.inT64 = waT; a.ybase = y; a.out64 = y; a.outT64 = cv.yT; a.alpha = h4;
+            a.obs = ob;
             if ((rc = launch_stage<true, false, BASE_Y, false, true>(t, s, a))) return rc;
         }
     } else {
@@ -1282,14 +1452,20 @@ int heom_propagate(const heom_tables *h, void *y_dev, void *work_dev, size_t wor
         for (int64_t st = 1; st <= nsteps; ++st) {
             double *ob = (obs_every > 0 && st % obs_every == 0) ? obs_dev + (st / obs_every) * HEOM_NOBS : nullptr;
             StageArgs a{};
-            a.in64 = y; a.out32 = u1; a.alpha = h1;
+            a.policy = pol;
+            a.in64 = y; a.inT64 = cv.yT; a.out32 = u1; a.outT32 = cv.u1T; a.alpha = h1;
             if ((rc = launch_stage<true, false, BASE_NONE, false, false>(t, s, a))) return rc;
-            a = StageArgs{}; a.in32 = u1; a.extra = u1; a.extra_scale = inv_h1; a.out32 = u2; a.alpha = h2;
+            a = StageArgs{}; a.policy = pol;
+            a.in32 = u1; a.inT32 = cv.u1T; a.extra = u1; a.extra_scale = inv_h1; a.out32 = u2;
+            a.outT32 = cv.u2T; a.alpha = h2;
             if ((rc = launch_stage<false, true, BASE_NONE, true, false>(t, s, a))) return rc;
-            a = StageArgs{}; a.in32 = u2; a.extra = u1; a.extra_scale = inv_h1; a.out32 = u3; a.alpha = h3;
+            a = StageArgs{}; a.policy = pol;
+            a.in32 = u2; a.inT32 = cv.u2T; a.extra = u1; a.extra_scale = inv_h1; a.out32 = u3;
+            a.outT32 = cv.u3T; a.alpha = h3;
             if ((rc = launch_stage<false, true, BASE_NONE, true, false>(t, s, a))) return rc;
-            a = StageArgs{}; a.in32 = u3; a.extra = u1; a.extra_scale = inv_h1; a.ybase = y; a.out64 = y;
-            a.alpha = h4; a.obs = ob;
+            a = StageArgs{}; a.policy = pol;
+            a.in32 = u3; a.inT32 = cv.u3T; a.extra = u1; a.extra_scale = inv_h1; a.ybase = y;
+            a.out64 = y; a.outT64 = cv.yT; a.alpha = h4; a.obs = ob;
             if ((rc = launch_stage<false, true, BASE_Y, true, true>(t, s, a))) return rc;
         }
     }
@@ -1299,16 +1475,24 @@ int heom_propagate(const heom_tables *h, void *y_dev, void *work_dev, size_t wor
 int heom_set_tuning(heom_tables *h, const heom_tuning *tu) {
     if (!h || !tu) return fail(HEOM_E_INVAL, "NULL argument");
     HostTables &t = h->t;
-    if (tu->tile_vars != 0 && tu->tile_vars != t.tile_vars) {
-        std::string err;
-        if (int rc = make_tiles(&t, tu->tile_vars, &err)) return fail(rc, err);
-    }
     if (tu->persistent < 0 || tu->persistent > 2) return fail(HEOM_E_INVAL, "persistent must be 0, 1 or 2");
+    if (tu->cache_policy < 0 || tu->cache_policy > 7) return fail(HEOM_E_INVAL, "cache_policy must be 0..7");
+    if (tu->transposed < -1 || tu->transposed > 1) return fail(HEOM_E_INVAL, "transposed must be -1, 0 or 1");
+    const bool trcol = tu->transposed < 0 ? t.n_var >= TRANSPOSED_MIN_VARS : tu->transposed != 0;
+    const int tv = tu->tile_vars != 0 ? tu->tile_vars : t.tile_vars;
+    const int old_mode = t.tune.transposed;
+    t.tune.transposed = tu->transposed;
+    if (tv != t.tile_vars || trcol != t.trcol) {
+        std::string err;
+        if (int rc = make_tiles(&t, tv, &err)) {
+            t.tune.transposed = old_mode;
+            return fail(rc, err);
+        }
+    }
     t.tune.persistent = tu->persistent;
     t.tune.xcd_map = tu->xcd_map ? 1 : 0;
     t.tune.max_workgroups = tu->max_workgroups;
     t.tune.spin_limit = tu->spin_limit;
-    if (tu->cache_policy < 0 || tu->cache_policy > 7) return fail(HEOM_E_INVAL, "cache_policy must be 0..7");
     t.tune.cache_policy = tu->cache_policy;
     return HEOM_OK;
 }
@@ -1318,7 +1502,7 @@ int heom_work_status(const heom_tables *h, const void *work_dev, size_t work_byt
     if (work_bytes < work_bytes_for(h->t)) return fail(HEOM_E_TOO_LARGE, "work buffer smaller than work_bytes");
     hipStream_t s = static_cast<hipStream_t>(stream);
     uint32_t flag = 0;
-    const unsigned char *p = static_cast<const unsigned char *>(work_dev) + 32 * (size_t)h->t.n_var + 4;
+    const unsigned char *p = static_cast<const unsigned char *>(work_dev) + vec_bytes(h->t) + 4;
     HIP_TRY(hipMemcpyAsync(&flag, p, 4, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     return flag ? fail(HEOM_E_TIMEOUT, "a grid barrier of the persistent kernel timed out") : HEOM_OK;
@@ -1332,6 +1516,7 @@ int heom_get_tuning(const heom_tables *h, heom_tuning *tu) {
     tu->max_workgroups = h->t.tune.max_workgroups;
     tu->spin_limit = h->t.tune.spin_limit;
     tu->cache_policy = h->t.tune.cache_policy;
+    tu->transposed = h->t.tune.transposed;
     return HEOM_OK;
 }
 
@@ -1446,6 +1631,7 @@ int heom_batch_set_slot(heom_batch *b, int32_t slot, const heom_tables *t, const
     S.params = params_dev ? params_dev : t->t.dev;
     S.y = y_dev;
     S.work = work_dev;
+    S.work_bytes = work_bytes;
     S.dt = dt;
     S.obs = obs_dev;
     S.obs_every = obs_every;
@@ -1481,6 +1667,13 @@ int heom_batch_commit(heom_batch *b, void *dev, size_t bytes, void *stream) {
     if (bytes < need) return fail(HEOM_E_TOO_LARGE, "batch buffer smaller than heom_batch_device_bytes");
     const size_t ns = b->slots.size();
     const size_t tile_off = (sizeof(SlotRec) * ns + 255) & ~(size_t)255;
+    // the tables of a slot may have been re-tuned since heom_batch_set_slot
+    for (const auto &S : b->slots) {
+        if (!S.used) continue;
+        if (int rc = check_ready(S.tables)) return rc;
+        if (S.work_bytes < work_bytes_for(S.tables->t))
+            return fail(HEOM_E_TOO_LARGE, "a slot's work buffer is smaller than its tables' work_bytes");
+    }
     std::vector<unsigned char> img(need, 0);
     SlotRec *recs = reinterpret_cast<SlotRec *>(img.data());
     BatchTile *tl = reinterpret_cast<BatchTile *>(img.data() + tile_off);
@@ -1489,7 +1682,6 @@ int heom_batch_commit(heom_batch *b, void *dev, size_t bytes, void *stream) {
         const BatchSlotHost &S = b->slots[i];
         if (!S.used) continue;
         const HostTables &t = S.tables->t;
-        const size_t n = t.n_var;
         SlotRec &R = recs[i];
         R.img = static_cast<const unsigned char *>(t.dev);
         R.params = static_cast<const unsigned char *>(S.params);
@@ -1500,13 +1692,19 @@ int heom_batch_commit(heom_batch *b, void *dev, size_t bytes, void *stream) {
         R.tiles = D.tiles;
         R.vrec = D.vrec;
         R.lut = reinterpret_cast<const double *>(R.params + reinterpret_cast<const InstParams *>(t.image.data())->off_lut);
-        unsigned char *wb = static_cast<unsigned char *>(S.work);
+        const WorkView wv = work_view(t, S.work);
         R.y = static_cast<double2 *>(S.y);
-        R.w0 = reinterpret_cast<double2 *>(wb);
-        R.w1 = R.w0 + n;
-        R.u1 = reinterpret_cast<float2 *>(wb + 16 * n);
-        R.u2 = R.u1 + n;
-        R.u3 = reinterpret_cast<float2 *>(wb);
+        R.w0 = wv.w0;
+        R.w1 = wv.w1;
+        R.u1 = wv.u1;
+        R.u2 = wv.u2;
+        R.u3 = wv.u3;
+        R.yT = wv.yT;
+        R.w0T = wv.w0T;
+        R.w1T = wv.w1T;
+        R.u1T = wv.u1T;
+        R.u2T = wv.u2T;
+        R.u3T = wv.u3T;
         R.obs = S.obs;
         R.obs_every = S.obs_every;
         R.obs_cap = S.obs_cap;
@@ -1621,8 +1819,17 @@ int heom_batch_propagate(heom_batch *b, int64_t nsteps, int precision, void *str
     if (!b) return fail(HEOM_E_INVAL, "batch is NULL");
     if (!b->committed) return fail(HEOM_E_STATE, "batch changed since the last heom_batch_commit");
     if (nsteps < 0) return fail(HEOM_E_INVAL, "nsteps < 0");
-    if (precision != HEOM_FP64 && precision != HEOM_FP32) return fail(HEOM_E_INVAL, "unknown precision");
+    const int base_prec = precision & ~HEOM_HERMITIAN;
+    if (base_prec != HEOM_FP64 && base_prec != HEOM_FP32) return fail(HEOM_E_INVAL, "unknown precision");
     hipStream_t s = static_cast<hipStream_t>(stream);
+    if (nsteps == 0) return HEOM_OK;
+    // slots with transposed copies: the copy of y, made once per call
+    // (Hermitian ADOs use no copies)
+    for (size_t i = 0; i < b->slots.size(); ++i) {
+        const BatchSlotHost &S = b->slots[i];
+        if (!S.used || !S.tables->t.trcol || (precision & HEOM_HERMITIAN)) continue;
+        if (int rc = launch_transpose(S.tables->t, s, b->recs[i].y, b->recs[i].yT)) return rc;
+    }
     int64_t done = 0;
     // Whole graphs of graph_steps steps where possible (not on the null
     // stream, which cannot be captured), single launches for the rest.

@@ -159,12 +159,16 @@ struct HostTables {
     int64_t hier_gathers = 0;
     std::vector<double> lut;            // up[k][n] then dn[k][n]
     std::vector<unsigned char> image;   // device image (host staging)
-    heom_tuning tune{0, 0, 0, 0, 0, 6};  // tile_vars unused here; persistent, xcd_map, max_workgroups, spin_limit, cache_policy
+    heom_tuning tune{0, 0, 0, 0, 0, 6, -1};  // tile_vars unused here; persistent, xcd_map, max_workgroups, spin_limit, cache_policy, transposed
+    bool trcol = false;                 // column gathers read the transposed copies (resolved from tune.transposed)
     uint32_t top_tile = 0;              // first tile whose patterns are all in tier L
     void *dev = nullptr;                // uploaded image
     size_t dev_bytes = 0;
     bool uploaded = false;
 };
+
+// States of at least this many variables keep transposed copies by default.
+constexpr uint32_t TRANSPOSED_MIN_VARS = 1u << 19;
 
 // host-side helpers implemented in tables.cpp
 int build(const heom_problem *p, HostTables *t, std::string *err);

@@ -415,6 +415,9 @@ static uint32_t tgt_index(const Conn &cr, int a, int b, bool same) {
 // target of a move of one molecule of category q by +-e_k is read through
 // the connection record of (q, k, direction): the moved molecule lies in q'
 // of the target, an unmoved molecule of category r in conn_remap(q, r).
+// With transposed copies (t.trcol) a column move names its target's position
+// in the transposed copy, which is the row-major position of the mirrored
+// entry (row and column categories exchanged; a T_q stays in place).
 void expand_gathers(const HostTables &t, uint32_t p, std::vector<uint32_t> *out) {
     const PatHdr &H = t.hdr[p];
     const int G = H.G, G1 = G + 1, M = t.m;
@@ -455,12 +458,10 @@ void expand_gathers(const HostTables &t, uint32_t p, std::vector<uint32_t> *out)
                 const int qn = (int)conn_q(c.info);
                 idx = kind == KIND_P ? tgt_index(c, qn, qn, true)
                                      : tgt_index(c, qn, kind == KIND_X ? -1 : conn_remap(c.info, q, r), false);
-            } else if (grp == 2) {   // column molecule raised
-                const Conn c = rup(cr, k);
-                idx = tgt_index(c, kind == KIND_Y ? -1 : conn_remap(c.info, r, q), (int)conn_q(c.info), false);
-            } else {                 // column molecule lowered
-                const Conn c = rdn(cr, k);
-                idx = tgt_index(c, kind == KIND_Y ? -1 : conn_remap(c.info, r, q), (int)conn_q(c.info), false);
+            } else {                 // column molecule raised (grp 2) or lowered (grp 3)
+                const Conn c = grp == 2 ? rup(cr, k) : rdn(cr, k);
+                const int ra = kind == KIND_Y ? -1 : conn_remap(c.info, r, q), cb = (int)conn_q(c.info);
+                idx = t.trcol ? tgt_index(c, cb, ra, false) : tgt_index(c, ra, cb, false);
             }
             out->push_back(idx);
         }
@@ -511,6 +512,7 @@ int make_tiles(HostTables *t, int tile_vars, std::string *err) {
         return HEOM_E_INVAL;
     }
     t->tile_vars = tile_vars;
+    t->trcol = t->tune.transposed < 0 ? t->n_var >= TRANSPOSED_MIN_VARS : t->tune.transposed != 0;
     t->tiles.clear();
     const size_t np = t->hdr.size();
     size_t i = 0;

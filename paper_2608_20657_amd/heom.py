@@ -21,6 +21,7 @@ HEOM_OK = 0
 HEOM_NOBS = 10
 HEOM_FP64 = 0
 HEOM_FP32 = 1
+HEOM_HERMITIAN = 2      # flag OR-ed into precision: every ADO is Hermitian
 ERRORS = {-1: "E_INVAL", -2: "E_NOMEM", -3: "E_TOO_LARGE", -4: "E_HIP", -5: "E_NONFINITE",
           -6: "E_UNSUPPORTED", -7: "E_STATE", -8: "E_TIMEOUT"}
 
@@ -53,7 +54,7 @@ class _Problem(ctypes.Structure):
 class _Tuning(ctypes.Structure):
     _fields_ = [("tile_vars", ctypes.c_int32), ("persistent", ctypes.c_int32), ("xcd_map", ctypes.c_int32),
                 ("max_workgroups", ctypes.c_int32), ("spin_limit", ctypes.c_int32),
-                ("cache_policy", ctypes.c_int32)]
+                ("cache_policy", ctypes.c_int32), ("transposed", ctypes.c_int32)]
 
 
 class _Sizes(ctypes.Structure):
@@ -61,7 +62,8 @@ class _Sizes(ctypes.Structure):
                 ("n_tiles", ctypes.c_int64), ("n_categories", ctypes.c_int64),
                 ("table_bytes", ctypes.c_int64), ("work_bytes_fp64", ctypes.c_int64),
                 ("work_bytes_fp32", ctypes.c_int64), ("tier0_size", ctypes.c_int64),
-                ("max_G", ctypes.c_int32), ("tile_vars", ctypes.c_int32), ("hier_gathers", ctypes.c_int64)]
+                ("max_G", ctypes.c_int32), ("tile_vars", ctypes.c_int32), ("hier_gathers", ctypes.c_int64),
+                ("rhs_work_bytes", ctypes.c_int64), ("transposed", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 def _load():
@@ -83,7 +85,7 @@ def _load():
         "heom_tier0_operator": [vp, dp, dp],
         "heom_tier0_expand": [vp, dp, dp],
         "heom_init_state": [vp, dp, vp, vp],
-        "heom_rhs": [vp, vp, vp, vp],
+        "heom_rhs": [vp, vp, vp, vp, ctypes.c_size_t, vp],
         "heom_propagate": [vp, vp, vp, ctypes.c_size_t, ctypes.c_double, i64, i64, vp, ctypes.c_int, vp],
         "heom_observables": [vp, vp, vp, vp],
         "heom_export_layout": [vp, ctypes.POINTER(i64), ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)],
@@ -234,8 +236,16 @@ class Tables:
         _check(LIB.heom_init_state(self._h, t0.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), _ptr(y),
                                    _stream(stream)))
 
-    def rhs(self, y, dy, stream=None):
-        _check(LIB.heom_rhs(self._h, _ptr(y), _ptr(dy), _stream(stream)))
+    def rhs(self, y, dy, stream=None, work=None):
+        """dy = M_u y. `work`: a device buffer of at least info()['rhs_work_bytes']
+        bytes (allocated here as a uint8 tensor if None and needed)."""
+        need = self.info()["rhs_work_bytes"]
+        if work is None and need > 0:
+            import torch
+            work = torch.empty(need, dtype=torch.uint8, device=y.device)
+        wbytes = work.numel() * work.element_size() if work is not None else 0
+        _check(LIB.heom_rhs(self._h, _ptr(y), _ptr(dy), _ptr(work) if work is not None else None, wbytes,
+                            _stream(stream)))
 
     def propagate(self, y, work, dt: float, nsteps: int, obs_every: int = 0, obs=None,
                   precision: int = HEOM_FP64, stream=None):
@@ -254,7 +264,8 @@ class Tables:
 
     def set_tuning(self, **kw):
         """Change launch knobs (tile_vars, persistent, xcd_map, max_workgroups,
-        spin_limit). A new tile_vars needs a new upload()."""
+        spin_limit, cache_policy, transposed). A new tile_vars or a change of
+        the transposed copies needs a new upload() and new work sizes."""
         cur = self.tuning()
         cur["tile_vars"] = 0
         cur.update(kw)

@@ -1,0 +1,196 @@
+"""GPU tests of the transposed copies (heom_tuning.transposed).
+
+With the copies on, every stage also writes its output with each block's
+category matrix transposed, and the column-molecule moves gather from that
+copy. The copy holds the same values and every variable sums its terms in
+the same order, so right-hand sides and trajectories must be bitwise those
+without copies; one right-hand side per case is also checked against the
+CPU oracle directly.
+"""
+import numpy as np
+import pytest
+
+from oracle import uvar
+from paper_2608_20657_amd import workloads as W
+from tests.gpu_util import gpu_propagate, gpu_rhs, named_tier0, rhs_bound, torch_cuda
+
+pytestmark = pytest.mark.gpu
+
+CASES = [(5, 2, 3, 1, "site1", False), (7, 3, 3, 0, "photon", True), (4, 1, 2, 2, "site1", True),
+         (6, 5, 2, 0, "photon", False), (64, 2, 6, 1, "site1", False), (3, 2, 4, 1, "site1", True)]
+
+
+def tables(p, transposed, tile_vars=0):
+    torch = torch_cuda()
+    from paper_2608_20657_amd import heom
+    T = heom.Tables(p)
+    kw = {"transposed": transposed}
+    if tile_vars:
+        kw["tile_vars"] = tile_vars
+    T.set_tuning(**kw)
+    info = T.info()
+    if transposed >= 0:
+        assert info["transposed"] == transposed
+    assert info["rhs_work_bytes"] == (16 * info["n_var"] if info["transposed"] else 0)
+    buf = torch.empty(info["table_bytes"], dtype=torch.uint8, device="cuda")
+    T.upload(buf, torch.cuda.current_stream())
+    return T, torch
+
+
+def problem(N, m, L, d, cc):
+    return W.random_problem(N, m, L, d, seed=N * 7 + m + L, complex_check=cc, loss=True, terminator=True)
+
+
+@pytest.mark.parametrize("N,m,L,d,state,cc", CASES)
+def test_rhs_transposed_bitwise_and_vs_oracle(N, m, L, d, state, cc):
+    p = problem(N, m, L, d, cc)
+    S = uvar.UVarSystem(p)
+    y = W.random_vector(S.n_var, seed=N + L)
+    T0, torch = tables(p, 0, tile_vars=64)
+    T1, _ = tables(p, 1, tile_vars=64)
+    a, b = gpu_rhs(T0, torch, y), gpu_rhs(T1, torch, y)
+    assert np.array_equal(a.view(np.float64), b.view(np.float64))
+    A = S.generator()
+    assert np.all(np.abs(b - A @ y) <= rhs_bound(A, y))
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("N,m,L,d,state,cc", CASES)
+def test_propagate_transposed_bitwise(N, m, L, d, state, cc, precision):
+    p = problem(N, m, L, d, cc)
+    out = []
+    for tr in (0, 1):
+        T, torch = tables(p, tr, tile_vars=64)
+        out.append(gpu_propagate(T, torch, named_tier0(T, p, state), 0.05, 23, 5, precision))
+    (y0, o0), (y1, o1) = out
+    assert np.array_equal(y0.view(np.float64), y1.view(np.float64))
+    assert np.array_equal(o0, o1)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_large_state_default_copies_bitwise(precision):
+    """1.56 M variables: copies on by default, top tier in its own launch."""
+    p = W.random_problem(100, 4, 8, 0, seed=3)
+    T1, torch = tables(p, -1)
+    assert T1.info()["transposed"] == 1 and T1.info()["n_tiles"] >= 2048
+    T0, _ = tables(p, 0)
+    t0 = named_tier0(T1, p, "photon")
+    y1, o1 = gpu_propagate(T1, torch, t0, 0.02, 6, 3, precision)
+    y0, o0 = gpu_propagate(T0, torch, t0, 0.02, 6, 3, precision)
+    assert np.array_equal(y0.view(np.float64), y1.view(np.float64))
+    assert np.array_equal(o0, o1)
+    yr = W.random_vector(T1.info()["n_var"], seed=5)
+    assert np.array_equal(gpu_rhs(T0, torch, yr).view(np.float64), gpu_rhs(T1, torch, yr).view(np.float64))
+
+
+def test_batch_mixes_slots_with_and_without_copies():
+    """A batch of slots with and without copies equals their solo runs."""
+    from paper_2608_20657_amd import heom
+    torch = torch_cuda()
+    s = torch.cuda.current_stream()
+    probs = [(5, 2, 3, 1, "site1", False, 1), (7, 3, 3, 0, "photon", True, 0), (64, 2, 6, 1, "site1", False, 1)]
+    steps, every, dt = 17, 4, 0.05
+    for precision in (0, 1):
+        b = heom.Batch(len(probs))
+        keep, want = [], []
+        for i, (N, m, L, d, state, cc, tr) in enumerate(probs):
+            p = problem(N, m, L, d, cc)
+            T, _ = tables(p, tr, tile_vars=64)
+            t0 = named_tier0(T, p, state)
+            want.append(gpu_propagate(T, torch, t0, dt, steps, every, precision))
+            info = T.info()
+            y = torch.empty(info["n_var"], dtype=torch.complex128, device="cuda")
+            T.init_state(t0, y, s)
+            work = torch.empty(info["work_bytes_fp64"], dtype=torch.uint8, device="cuda")
+            obs = torch.zeros((steps // every + 1) * 10, dtype=torch.float64, device="cuda")
+            b.set_slot(i, T, y, work, dt, obs=obs, obs_every=every)
+            keep.append((T, y, work, obs))
+        b.commit(torch, s)
+        b.propagate(steps, precision, s)
+        torch.cuda.synchronize()
+        for (T, y, work, obs), (wy, wo) in zip(keep, want):
+            assert np.array_equal(y.cpu().numpy().view(np.float64), wy.view(np.float64))
+            assert np.array_equal(obs.cpu().numpy().reshape(-1, 10), wo)
+
+
+# Hermitian ADOs (HEOM_HERMITIAN): column gathers read the conjugated mirrored
+# entry of the row-major state itself. The mirrored entries are computed by
+# different threads, so results agree with the general path to rounding.
+HERM = [(5, 2, 3, 1, "site1"), (7, 3, 3, 0, "photon"), (4, 1, 2, 2, "site1"), (64, 2, 6, 1, "upper_polariton"),
+        (6, 5, 2, 0, "photon")]
+
+
+def herm_problem(N, m, L, d):
+    return W.random_problem(N, m, L, d, seed=N * 5 + m + L, complex_check=False, loss=True, terminator=True)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("N,m,L,d,state", HERM)
+def test_hermitian_mirror_matches_general(N, m, L, d, state, precision):
+    from paper_2608_20657_amd import heom
+    p = herm_problem(N, m, L, d)
+    Tg, torch = tables(p, 0, tile_vars=64)
+    Th, _ = tables(p, 1, tile_vars=64)
+    t0 = named_tier0(Tg, p, state)
+    yg, og = gpu_propagate(Tg, torch, t0, 0.05, 23, 5, precision)
+    yh, oh = gpu_propagate(Th, torch, t0, 0.05, 23, 5, precision | heom.HEOM_HERMITIAN)
+    tol = 1e-12 if precision == 0 else 1e-6
+    scale = np.abs(yg).max()
+    assert np.abs(yh - yg).max() <= tol * scale
+    assert np.abs(oh - og).max() <= tol * max(1.0, np.abs(og).max())
+    # the flag is ignored by tables without transposed copies: bitwise the general path
+    yn, on = gpu_propagate(Tg, torch, t0, 0.05, 23, 5, precision | heom.HEOM_HERMITIAN)
+    assert np.array_equal(yn.view(np.float64), yg.view(np.float64)) and np.array_equal(on, og)
+
+
+def test_hermitian_mirror_large_state():
+    from paper_2608_20657_amd import heom
+    p = W.random_problem(100, 4, 8, 0, seed=3)
+    Th, torch = tables(p, -1)
+    Tg, _ = tables(p, 0)
+    t0 = named_tier0(Tg, p, "photon")
+    yg, og = gpu_propagate(Tg, torch, t0, 0.02, 6, 3, 0)
+    yh, oh = gpu_propagate(Th, torch, t0, 0.02, 6, 3, heom.HEOM_HERMITIAN)
+    assert np.abs(yh - yg).max() <= 1e-12 * np.abs(yg).max()
+    assert np.abs(oh - og).max() <= 1e-12
+
+
+def test_hermitian_flag_needs_adjoint_preserving_bath():
+    from paper_2608_20657_amd import heom
+    p = W.random_problem(5, 2, 3, 1, seed=2, complex_check=True)
+    T, torch = tables(p, 1, tile_vars=64)
+    with pytest.raises(heom.HeomError) as e:
+        gpu_propagate(T, torch, named_tier0(T, p, "site1"), 0.05, 3, 1, heom.HEOM_HERMITIAN)
+    assert e.value.code == -1
+
+
+def test_batch_hermitian_equals_solo():
+    """Batch slots with and without transposed tables, Hermitian flag: each
+    equals its own heom_propagate run with the flag, bitwise."""
+    from paper_2608_20657_amd import heom
+    torch = torch_cuda()
+    s = torch.cuda.current_stream()
+    probs = [(5, 2, 3, 1, "site1", 1), (7, 3, 3, 0, "photon", 0), (64, 2, 6, 1, "site1", 1)]
+    steps, every, dt = 17, 4, 0.05
+    for precision in (0, 1):
+        flag = precision | heom.HEOM_HERMITIAN
+        b = heom.Batch(len(probs))
+        keep, want = [], []
+        for i, (N, m, L, d, state, tr) in enumerate(probs):
+            p = herm_problem(N, m, L, d)
+            T, _ = tables(p, tr, tile_vars=64)
+            t0 = named_tier0(T, p, state)
+            want.append(gpu_propagate(T, torch, t0, dt, steps, every, flag))
+            info = T.info()
+            y = torch.empty(info["n_var"], dtype=torch.complex128, device="cuda")
+            T.init_state(t0, y, s)
+            work = torch.empty(info["work_bytes_fp64"], dtype=torch.uint8, device="cuda")
+            obs = torch.zeros((steps // every + 1) * 10, dtype=torch.float64, device="cuda")
+            b.set_slot(i, T, y, work, dt, obs=obs, obs_every=every)
+            keep.append((T, y, work, obs))
+        b.commit(torch, s)
+        b.propagate(steps, flag, s)
+        torch.cuda.synchronize()
+        for (T, y, work, obs), (wy, wo) in zip(keep, want):
+            assert np.array_equal(y.cpu().numpy().view(np.float64), wy.view(np.float64))
+            assert np.array_equal(obs.cpu().numpy().reshape(-1, 10), wo)

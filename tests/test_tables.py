@@ -153,3 +153,25 @@ def test_paper_shape_table_sizes(N, d, patterns, unique):
     info = heom.Tables(W.config_paper_shape(N, d)).info()
     assert info["n_patterns"] == patterns
     assert info["n_var"] == unique
+
+
+def test_transposed_copies_sizes_and_knob():
+    """The transposed-copy knob: off by default below 2^19 variables; on, the
+    work buffers grow by three FP64 state vectors and heom_rhs asks for one;
+    the table image keeps its size (the same gather lists, other targets)."""
+    p = W.random_problem(5, 2, 3, 1, seed=1)
+    T = heom.Tables(p)
+    i0 = T.info()
+    assert i0["transposed"] == 0 and i0["rhs_work_bytes"] == 0
+    assert T.tuning()["transposed"] == -1
+    T.set_tuning(transposed=1)
+    i1 = T.info()
+    assert i1["transposed"] == 1 and i1["rhs_work_bytes"] == 16 * i1["n_var"]
+    assert i1["work_bytes_fp64"] - i0["work_bytes_fp64"] == 48 * i1["n_var"]
+    assert i1["work_bytes_fp32"] == i1["work_bytes_fp64"]
+    assert i1["table_bytes"] == i0["table_bytes"]
+    T.set_tuning(transposed=-1)
+    assert T.info()["transposed"] == 0
+    with pytest.raises(heom.HeomError):
+        T.set_tuning(transposed=2)
+    assert T.tuning()["transposed"] == -1
