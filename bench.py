@@ -189,7 +189,7 @@ def batched_section(torch, steps, n=512, seed=0, dt=0.02, flag=0):
            "instances": len(inst), "unique_vars_total": nv, "structure_keys": len(structs),
            "largest_instance_vars": max(x[6] for x in inst),
            "median_instance_vars": int(sorted(x[6] for x in inst)[len(inst) // 2]),
-           "steps": steps, "table_build_s": round(build_s, 2)}
+           "steps": steps, "table_build_s": round(build_s, 2), "hermitian_ados": bool(flag)}
     for prec, name in ((0, "fp64_batched"), (1, "fp32_batched")):
         for q, T, params, y, work, t0v, _ in inst:
             T.init_state(t0v, y, st)
@@ -230,7 +230,7 @@ def batched_section(torch, steps, n=512, seed=0, dt=0.02, flag=0):
 
 
 def serving_point(torch, rate, window, deadline, seed=1, precision=0, budget_gib=256.0,
-                  lanes=(1 << 20,), capacity=(256, 32), fifo=True):
+                  lanes=(1 << 20,), capacity=(256, 32), fifo=True, flag=0):
     """Poisson arrivals of propagation requests (problems drawn as in the
     batched workload, plus a horizon of U{1000..20000} steps, obs every 100
     steps, dt=0.02). Arrivals in [0, window) are submitted; the run ends at
@@ -246,20 +246,22 @@ def serving_point(torch, rate, window, deadline, seed=1, precision=0, budget_gib
            "rate_req_per_s": rate, "window_s": window, "deadline_s": deadline, "requests": len(reqs),
            "offered_rhs_updates_per_s": None}
     srv = S.Server(torch, int(budget_gib * (1 << 30)), lanes=list(lanes), capacity=list(capacity),
-                   precision=precision)
+                   precision=precision | flag)
     srv.prepare(ps)
     work = sum(srv.structs[S.structure_key(q)].n_var * 4 * r.horizon for q, r in zip(ps, reqs))
     out["offered_rhs_updates_per_s"] = work / window
     st = srv.run(reqs, window, deadline)
     st["precision"] = "fp32-bulk" if precision == 1 else "fp64"
+    st["hermitian_ados"] = bool(flag)
     st["budget_gib"] = budget_gib
     st["lanes_vars_threshold"] = list(lanes)
     out["served"] = st
     if fifo:
-        ff = S.Fifo(torch, precision=0)
+        ff = S.Fifo(torch, precision=flag)
         ff.prepare(ps)
         st2 = ff.run(reqs, window, deadline)
         st2["precision"] = "fp64"
+        st2["hermitian_ados"] = bool(flag)
         out["plain_fifo"] = st2
         got = {r.rid: r.obs for r in srv.results}
         errs = [float(np.abs(got[r.rid][:, POP_COLS] - r.obs[:, POP_COLS]).max()) for r in ff.results if r.rid in got]
@@ -297,6 +299,10 @@ def main():
                     help="arithmetic of the continuous-batching server (the plain baseline is always FP64)")
     ap.add_argument("--serve-sweep", type=str, default="",
                     help="comma-separated arrival rates: print one serving JSON line per rate and exit")
+    ap.add_argument("--general", action="store_true",
+                    help="do not assert Hermitian ADOs (every workload here starts from a Hermitian rho_S(0) "
+                         "with c_check = conj(c), so by default column gathers of large states read mirrored "
+                         "entries; this switch uses the general transposed-copy path)")
     ap.add_argument("--calibrate-copy-mb", type=int, default=0,
                     help="also run a plain device-to-device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -313,10 +319,11 @@ def main():
     from paper_2608_20657_amd import heom, workloads as W
 
     precision = 0 if args.precision == "fp64" else 1
+    herm = 0 if args.general else heom.HEOM_HERMITIAN
     if args.serve_sweep:
         for r in [float(x) for x in args.serve_sweep.split(",") if x]:
             rec = serving_point(torch, r, args.serve_window, args.serve_deadline,
-                                precision=0 if args.serve_precision == "fp64" else 1)
+                                precision=0 if args.serve_precision == "fp64" else 1, flag=herm)
             print(json.dumps({"serving_sweep_point": rec}), flush=True)
         return
     if args.calibrate_copy_mb:
@@ -346,7 +353,7 @@ def main():
     info = T.info()
     if args.roofline_only:
         args.steps, args.warmup = 1, 0
-    ms, wall, y, obs = time_propagate(T, torch, tier0, dt, args.steps, args.warmup, args.obs_every, precision)
+    ms, wall, y, obs = time_propagate(T, torch, tier0, dt, args.steps, args.warmup, args.obs_every, precision | herm)
     n = info["n_var"]
     updates = n * 4 * args.steps
     value = updates / (ms / 1e3)
@@ -377,7 +384,7 @@ def main():
         "config": {"workload": "localized: N=64, m=2 (Debye + 1 Matsubara, lam=0.02, gam=0.1, kT=0.025), "
                                "L=6, d=1, g=0.01, eps-omega_c=0.01, kappa=0.005, rho(0)=|e_1><e_1|, dt=0.02",
                    "n_var": n, "patterns": info["n_patterns"], "rhs_per_step": 4,
-                   "obs_every": args.obs_every, "precision": args.precision,
+                   "obs_every": args.obs_every, "precision": args.precision, "hermitian_ados": not args.general,
                    "parallelism": "single GPU"},
         "wall_s": round(wall, 4),
         "finite": finite,
@@ -396,7 +403,7 @@ def main():
         img2 = torch.empty(ri["table_bytes"], dtype=torch.uint8, device="cuda")
         TR.upload(img2, torch.cuda.current_stream())
         t0r = TR.tier0_pure(1.0, 0.0, [])
-        rms, _, ry, _ = time_propagate(TR, torch, t0r, dt, args.roofline_steps, 3, 0, 0)
+        rms, _, ry, _ = time_propagate(TR, torch, t0r, dt, args.roofline_steps, 3, 0, herm)
         launch_ms = rms / (4 * args.roofline_steps)
         bytes_launch = ri["n_var"] * stage_bytes_per_var(0) / 4.0 + ri["table_bytes"]
         achieved = bytes_launch / (launch_ms * 1e-3) / 1e9
@@ -407,6 +414,7 @@ def main():
             "traffic": traffic["bytes_per_launch"] if traffic else None,
             "kernel": "stage_kernel, FP64 RK4 stage (RHS + combination); one stage = the lower-tier launch "
                       "plus the top-tier launch; mean over the 4 stages of a step",
+            "column_gathers": "mirrored (Hermitian ADOs)" if herm else "transposed copy",
             "workload": "roofline probe: N=10^4, m=4, L=10, d=0 (17,347,066 unique variables, "
                         "278 MB per FP64 vector)",
             "algorithmic_bytes_per_launch": int(bytes_launch),
@@ -420,10 +428,10 @@ def main():
     if args.roofline_only:
         args.no_batched = args.no_serve = True
     if not args.no_batched:
-        out["batched"] = batched_section(torch, args.batched_steps)
+        out["batched"] = batched_section(torch, args.batched_steps, flag=herm)
     if not args.no_serve:
         out["serving"] = serving_point(torch, args.serve_rate, args.serve_window, args.serve_deadline,
-                                       precision=0 if args.serve_precision == "fp64" else 1)
+                                       precision=0 if args.serve_precision == "fp64" else 1, flag=herm)
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(p, lambda i: 1.0 if i == 1 else 0.0, dt, args.cpu_seconds)

@@ -429,7 +429,12 @@ __device__ __forceinline__ void process_tile(const InstParams &P, const Dev &D, 
         const int L1 = P.L + 1;
         const double *up = S.lut;
         const double *dn = S.lut + M * L1;
-        const double cs = (a.policy & 8u) ? -1.0 : 1.0;   // mirrored column gathers: conjugate
+        // mirrored column gathers are conjugated: sign bit of the imaginary part
+        const uint32_t csign = (a.policy & 8u) ? 0x80000000u : 0u;
+        auto conj_if = [&](double2 w) {
+            const uint64_t b = (uint64_t)__double_as_longlong(w.y) ^ ((uint64_t)csign << 32);
+            return make_double2(w.x, __longlong_as_double((long long)b));
+        };
 #pragma unroll
         for (int k = 0; k < M; ++k) {
             const uint32_t nq = vbyte(cq.vec, k), nr = vbyte(cr2.vec, k);
@@ -438,12 +443,8 @@ __device__ __forceinline__ void process_tile(const InstParams &P, const Dev &D, 
             const double cim = kind == KIND_P ? P.ci[k] - P.cci[k] : P.ci[k];
             if (!TOP) cfma(hier, make_double2(0.0, -up[k * L1 + nq]), gv(k));
             cfma(hier, make_double2(dq * cim, -dq * cre), gv(M + k));
-            if (!TOP) {
-                const double2 w = gv(2 * M + k);
-                cfma(hier, make_double2(0.0, up[k * L1 + nr]), make_double2(w.x, cs * w.y));
-            }
-            const double2 w = gv(3 * M + k);
-            cfma(hier, make_double2(-dr * P.cci[k], dr * P.ccr[k]), make_double2(w.x, cs * w.y));
+            if (!TOP) cfma(hier, make_double2(0.0, up[k * L1 + nr]), conj_if(gv(2 * M + k)));
+            cfma(hier, make_double2(-dr * P.cci[k], dr * P.ccr[k]), conj_if(gv(3 * M + k)));
         }
     }
     double *md = S.md + (H.cat_base - TR.c0);

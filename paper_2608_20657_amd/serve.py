@@ -212,7 +212,9 @@ class Server:
     budget_bytes: HBM the server may hold (requests and table images).
     lanes: ascending unique-variable thresholds splitting requests into
     len(lanes)+1 lanes. capacity: slots per lane (an int or one per lane).
-    precision: HEOM_FP64 or HEOM_FP32 (FP32 bulk with FP64 state).
+    precision: HEOM_FP64 or HEOM_FP32 (FP32 bulk with FP64 state), with
+    HEOM_HERMITIAN OR-ed in when every request's ADOs are Hermitian (a
+    Hermitian rho_S(0) and c_check = conj(c)).
     target_ms: device time per chunk; sets how long an arrival waits for
     its lane's next chunk boundary."""
 
