@@ -95,8 +95,10 @@ typedef struct heom_sizes {
     int32_t tile_vars;       /* variables per tile (workgroup size) */
     int64_t hier_gathers;    /* hierarchy reads of one right-hand side */
     int64_t rhs_work_bytes;  /* device work bytes heom_rhs needs (0 without transposed copies) */
-    int32_t transposed;      /* 1 if the kernels keep transposed copies (see heom_tuning) */
-    int32_t reserved;
+    int32_t transposed;      /* 1 if column moves name transposed positions (see heom_tuning) */
+    int32_t compact;         /* 1 if the tiles are compact (see heom_tuning) */
+    int64_t stage_table_bytes; /* bytes of the table image one stage reads (compact tiles leave the
+                                  record slots of their mirrored entries unread) */
 } heom_sizes;
 
 /* Build the pattern list, unique-variable layout and connection tables of
@@ -253,6 +255,18 @@ typedef struct heom_tuning {
                                 from that copy, where the entries one column move reads are
                                 contiguous; work_bytes grow from 32 to 80 bytes per variable and the
                                 persistent launch is not used. */
+    int32_t compact;         /* 1: compact tiles for Hermitian ADOs (default 0). Each block's lower
+                                triangle (row > column) is the conjugate of its upper triangle, so
+                                the threads cover only the entries with row <= column and the T_q;
+                                each writes its entry and the conjugate into the mirrored position,
+                                and the column sums of the Hamiltonian bracket are taken as the
+                                conjugates of the row sums (Eqs. grouped-row-sum,
+                                grouped-column-sum). About half the gathers and arithmetic of a
+                                stage. Implies transposed column targets, with no copies (work_bytes
+                                stay 32 per variable). The upper triangle of y is taken as the
+                                state. Only heom_propagate / heom_batch_propagate with
+                                HEOM_HERMITIAN run on such tables (E_STATE otherwise, heom_rhs
+                                included). */
 } heom_tuning;
 
 /* Set or read the launch configuration. A new tile_vars or a change of the

@@ -256,8 +256,8 @@ struct Smem {
 __device__ __forceinline__ Smem carve(unsigned char *smem, const InstParams &P) {
     Smem S;
     S.val = reinterpret_cast<double2 *>(smem);
-    S.rc = S.val + P.tile_vars;
-    S.hdr = reinterpret_cast<PatHdr *>(smem + 32u * P.tile_vars);
+    S.rc = S.val + P.val_len;
+    S.hdr = reinterpret_cast<PatHdr *>(smem + 32u * P.val_len);
     S.cat = reinterpret_cast<CatRec *>(S.hdr + P.max_np);
     S.gix = reinterpret_cast<uint32_t *>(S.cat + P.max_nc);
     S.lut = reinterpret_cast<double *>(S.gix + ((P.max_ng + 3u) & ~3u));
@@ -354,19 +354,32 @@ __device__ __forceinline__ double2 load_own(const StageArgs &a, uint32_t j) {
 //    so the loop body has no branches.
 // 4. Every thread reads its Hamiltonian bracket from LDS, adds damping,
 //    loss, the terminator and the extra term, and writes the combination.
-template <int M, bool HAS64, bool HAS32, int BASE, bool EXTRA, bool OUT64, bool TOP>
+template <int M, bool HAS64, bool HAS32, int BASE, bool EXTRA, bool OUT64, bool TOP, int CM>
 __device__ __forceinline__ void process_tile(const InstParams &P, const Dev &D, const TileRec &TR, const Smem &S,
                                              const StageArgs &a, bool first_tile, bool stage, uint32_t lut_w) {
     const uint32_t t = threadIdx.x;
     const bool active = t < TR.nv;
+    // compact tiles: this thread's entry is variable vt of the tile (row <=
+    // column or a T_q); it also owns the mirrored entry, the conjugate.
+    // CM: 0 plain tiles, 1 compact tiles, 2 as the parameter block says
+    // (batches, whose slots may differ)
+    const bool cmp = CM == 2 ? P.compact != 0 : CM == 1;
+    uint32_t vt = t;
     double2 own = make_double2(0.0, 0.0), ybv = make_double2(0.0, 0.0);
     float2 ex = make_float2(0.0f, 0.0f);
     VarRec vr{0u, 0u};
     if (active) {
         vr = D.vrec[TR.v0 + t];
-        own = load_own<HAS64, HAS32>(a, TR.v0 + t);
-        if (BASE == BASE_Y) ybv = (a.policy & 2u) ? ld_stream(a.ybase + TR.v0 + t) : a.ybase[TR.v0 + t];
-        if (EXTRA) ex = a.extra[TR.v0 + t];
+        if (cmp) {
+            // the compact index list of the structure image (located from the
+            // header section: a parameter block shares the image's offsets)
+            const uint16_t *vloc = reinterpret_cast<const uint16_t *>(
+                reinterpret_cast<const unsigned char *>(D.hdr) + (P.off_vloc - P.off_hdr));
+            vt = vloc[TR.v0 + t];
+        }
+        own = load_own<HAS64, HAS32>(a, TR.v0 + vt);
+        if (BASE == BASE_Y) ybv = (a.policy & 2u) ? ld_stream(a.ybase + TR.v0 + vt) : a.ybase[TR.v0 + vt];
+        if (EXTRA) ex = a.extra[TR.v0 + vt];
     }
     if (stage) stage_tile(D, TR, S, lut_w);
     __syncthreads();
@@ -375,8 +388,12 @@ __device__ __forceinline__ void process_tile(const InstParams &P, const Dev &D, 
     const bool isT = (vr.x >> 17) & 1u;
     const uint32_t goff = vr.x >> 18, live = vr.y;
     const PatHdr H = S.hdr[p];
-    const uint32_t base = H.off - TR.v0, loc = t - base;
+    const uint32_t base = H.off - TR.v0, loc = vt - base;
     const int G = H.G, G1 = G + 1, nm = G1 * G1;
+    // position of the mirrored entry (row and column exchanged) in the tile,
+    // for compact tiles' off-diagonal entries
+    const bool has_mirror = cmp && A != B && !isT;
+    const uint32_t vmir = base + B * (uint32_t)G1 + A;
     const int kind = (A == 0 && B == 0) ? KIND_Z : (B == 0 ? KIND_X : (A == 0 ? KIND_Y : ((A == B && !isT) ? KIND_P : KIND_S)));
     const CatRec *cats = S.cat + (H.cat_base - TR.c0);
     double2 hier = make_double2(0.0, 0.0);
@@ -423,7 +440,8 @@ __device__ __forceinline__ void process_tile(const InstParams &P, const Dev &D, 
             }
             return r;
         };
-        S.val[t] = own;
+        S.val[vt] = own;
+        if (has_mirror) S.val[vmir] = make_double2(own.x, -own.y);
         // row moves -i sqrt((n+1)|c|), -i sqrt(n/|c|) c_k (P: c_k - cc_k);
         // column moves +i sqrt((n+1)|c|), +i sqrt(n/|c|) cc_k
         const int L1 = P.L + 1;
@@ -454,7 +472,9 @@ __device__ __forceinline__ void process_tile(const InstParams &P, const Dev &D, 
     }
     __syncthreads();
 
-    if (active && loc < (uint32_t)(2 * G + 1)) {
+    // compact tiles: only the row sums R_c (lanes 1..G, the entries (0, c+1));
+    // the column sums of a Hermitian block are their conjugates
+    if (active && loc < (uint32_t)(cmp ? G + 1 : 2 * G + 1)) {
         const bool isZ = loc == 0, isRow = loc <= (uint32_t)G;
         const int c = isZ ? -1 : (isRow ? (int)loc - 1 : (int)loc - 1 - G);
         // Z: entries (x+1, 0) minus (0, x+1); R_c: (c+1, x+1); C_c: (x+1, c+1)
@@ -487,14 +507,17 @@ __device__ __forceinline__ void process_tile(const InstParams &P, const Dev &D, 
         // Hamiltonian bracket (multiplied by -i g below):
         //   Z: sum_q M_q (X_q - Y_q)   X_q: Z - R_q   Y_r: C_r - Z
         //   P_q: Y_q - X_q             S_qr, T_q: Y_r - X_q
-        const double2 *VR = S.val;   // S.rc follows S.val: index tile_vars + i is rc[i]
-        const uint32_t tv = P.tile_vars;
+        // (compact tiles: C_r = conj(R_r))
+        const double2 *VR = S.val;   // S.rc follows S.val: index val_len + i is rc[i]
+        const uint32_t vl = P.val_len;
         uint32_t i1, i2;
-        if (kind == KIND_Z) { i1 = tv + base; i2 = base; }
-        else if (kind == KIND_X) { i1 = base; i2 = tv + base + A; }
-        else if (kind == KIND_Y) { i1 = tv + base + G + B; i2 = base; }
+        if (kind == KIND_Z) { i1 = vl + base; i2 = base; }
+        else if (kind == KIND_X) { i1 = base; i2 = vl + base + A; }
+        else if (kind == KIND_Y) { i1 = vl + base + (cmp ? 0u : (uint32_t)G) + B; i2 = base; }
         else { i1 = base + B; i2 = base + A * G1; }
-        const double2 h1 = VR[i1], h2 = kind == KIND_Z ? make_double2(0.0, 0.0) : VR[i2];
+        double2 h1 = VR[i1];
+        const double2 h2 = kind == KIND_Z ? make_double2(0.0, 0.0) : VR[i2];
+        if (cmp && kind == KIND_Y) h1.y = -h1.y;
         const double2 hsum = csub(h1, h2);
         double gam = 0.0;
 #pragma unroll
@@ -516,16 +539,25 @@ __device__ __forceinline__ void process_tile(const InstParams &P, const Dev &D, 
         res = cscale(a.alpha, acc);
         if (BASE == BASE_IN) res = cadd(res, own);
         if (BASE == BASE_Y) res = cadd(res, ybv);
+        const double2 rc = make_double2(res.x, -res.y);
         if (a.policy & 4u) {
-            if (OUT64) st_stream(a.out64 + TR.v0 + t, res);
-            else st_stream(a.out32 + TR.v0 + t, res);
+            if (OUT64) st_stream(a.out64 + TR.v0 + vt, res);
+            else st_stream(a.out32 + TR.v0 + vt, res);
+            if (has_mirror) {
+                if (OUT64) st_stream(a.out64 + TR.v0 + vmir, rc);
+                else st_stream(a.out32 + TR.v0 + vmir, rc);
+            }
         } else {
-            if (OUT64) a.out64[TR.v0 + t] = res;
-            else a.out32[TR.v0 + t] = make_float2((float)res.x, (float)res.y);
+            if (OUT64) a.out64[TR.v0 + vt] = res;
+            else a.out32[TR.v0 + vt] = make_float2((float)res.x, (float)res.y);
+            if (has_mirror) {
+                if (OUT64) a.out64[TR.v0 + vmir] = rc;
+                else a.out32[TR.v0 + vmir] = make_float2((float)rc.x, (float)rc.y);
+            }
         }
         if (OUT64 ? a.outT64 != nullptr : a.outT32 != nullptr) {
             // position of this entry in the transposed copy (T_q in place)
-            const uint32_t tp = TR.v0 + (isT ? t : base + B * (uint32_t)G1 + A);
+            const uint32_t tp = TR.v0 + (isT ? vt : vmir);
             if (a.policy & 4u) {
                 if (OUT64) st_stream(a.outT64 + tp, res);
                 else st_stream(a.outT32 + tp, res);
@@ -540,7 +572,10 @@ __device__ __forceinline__ void process_tile(const InstParams &P, const Dev &D, 
         // the empty pattern is the first block of tile 0: evaluate the
         // observables of the freshly computed tier-0 block
         const uint32_t n0 = S.hdr[0].size;
-        if (t < n0) S.val[t] = res;
+        if (active && vt < n0) {
+            S.val[vt] = res;
+            if (has_mirror) S.val[vmir] = make_double2(res.x, -res.y);
+        }
         __syncthreads();
         if (t == 0) tier0_observables(P, S.hdr[0], S.cat, S.val, a.obs);
         __syncthreads();
@@ -549,14 +584,14 @@ __device__ __forceinline__ void process_tile(const InstParams &P, const Dev &D, 
 
 // One launch = one stage over all tiles (used by heom_rhs and as the
 // non-persistent path).
-template <int M, bool HAS64, bool HAS32, int BASE, bool EXTRA, bool OUT64, bool TOP>
+template <int M, bool HAS64, bool HAS32, int BASE, bool EXTRA, bool OUT64, bool TOP, int CM>
 __global__ __launch_bounds__(MAX_TILE) void stage_kernel(Dev D, StageArgs a, int xcd) {
     extern __shared__ __align__(16) unsigned char smem[];
     const InstParams &P = *D.ip;
     const Smem S = carve(smem, P);
     const uint32_t tile = a.tile0 + (xcd ? xcd_tile(blockIdx.x, gridDim.x) : blockIdx.x);
     const TileRec TR = D.tiles[tile];
-    process_tile<M, HAS64, HAS32, BASE, EXTRA, OUT64, TOP>(P, D, TR, S, a, tile == 0, true, lut_words(P));
+    process_tile<M, HAS64, HAS32, BASE, EXTRA, OUT64, TOP, CM>(P, D, TR, S, a, tile == 0, true, lut_words(P));
 }
 
 // Grid-wide barrier for the persistent kernel. Workgroup w publishes its
@@ -665,12 +700,12 @@ __global__ __launch_bounds__(MAX_TILE) void persistent_kernel(Dev D, PersistArgs
                 const TileRec TR = single ? TR0 : D.tiles[tl];
                 const bool sd = !single;   // one tile per workgroup: staged once above
                 if (PREC == HEOM_FP64) {
-                    if (s == 0) process_tile<M, true, false, BASE_IN, false, true, false>(P, D, TR, S, a, tl == 0, sd, 0u);
-                    else process_tile<M, true, false, BASE_Y, false, true, false>(P, D, TR, S, a, tl == 0, sd, 0u);
+                    if (s == 0) process_tile<M, true, false, BASE_IN, false, true, false, 0>(P, D, TR, S, a, tl == 0, sd, 0u);
+                    else process_tile<M, true, false, BASE_Y, false, true, false, 0>(P, D, TR, S, a, tl == 0, sd, 0u);
                 } else {
-                    if (s == 0) process_tile<M, true, false, BASE_NONE, false, false, false>(P, D, TR, S, a, false, sd, 0u);
-                    else if (s < 3) process_tile<M, false, true, BASE_NONE, true, false, false>(P, D, TR, S, a, false, sd, 0u);
-                    else process_tile<M, false, true, BASE_Y, true, true, false>(P, D, TR, S, a, tl == 0, sd, 0u);
+                    if (s == 0) process_tile<M, true, false, BASE_NONE, false, false, false, 0>(P, D, TR, S, a, false, sd, 0u);
+                    else if (s < 3) process_tile<M, false, true, BASE_NONE, true, false, false, 0>(P, D, TR, S, a, false, sd, 0u);
+                    else process_tile<M, false, true, BASE_Y, true, true, false, 0>(P, D, TR, S, a, tl == 0, sd, 0u);
                 }
             }
             epoch += 1;
@@ -751,9 +786,9 @@ __device__ __forceinline__ BatchCtx batch_ctx(const SlotRec &rec, uint32_t tile,
     const int64_t gst = s == 3 ? R.step0 + *as_global(ctr) : 0;
     StageArgs &a = c.a;
     a = StageArgs{};
-    // mirrored column gathers need transposed tables (R.yT is set exactly
-    // then); with them, the slot neither reads nor writes copies
-    const bool trcol = R.yT != nullptr, mirror = (policy & 8u) && trcol;
+    // mirrored column gathers need transposed column targets; with them the
+    // slot neither reads nor writes copies
+    const bool mirror = (policy & 8u) && P.tcol != 0;
     a.policy = mirror ? policy : (policy & ~8u);
     if (mirror) R.yT = R.w0T = R.w1T = nullptr, R.u1T = R.u2T = R.u3T = nullptr;
     a.alpha = s == 0 ? h / 4.0 : (s == 1 ? h / 3.0 : (s == 2 ? h / 2.0 : h));
@@ -790,12 +825,12 @@ __device__ __forceinline__ void batch_tile(const BatchCtx &c, unsigned char *sme
     const Smem S = carve(smem, P);
     const uint32_t lw = lut_words(P);
     if (PREC == HEOM_FP64) {
-        if (SV == 0) process_tile<M, true, false, BASE_IN, false, true, TOP>(P, c.D, c.TR, S, c.a, c.first, true, lw);
-        else process_tile<M, true, false, BASE_Y, false, true, TOP>(P, c.D, c.TR, S, c.a, c.first, true, lw);
+        if (SV == 0) process_tile<M, true, false, BASE_IN, false, true, TOP, 2>(P, c.D, c.TR, S, c.a, c.first, true, lw);
+        else process_tile<M, true, false, BASE_Y, false, true, TOP, 2>(P, c.D, c.TR, S, c.a, c.first, true, lw);
     } else {
-        if (SV == 0) process_tile<M, true, false, BASE_NONE, false, false, TOP>(P, c.D, c.TR, S, c.a, false, true, lw);
-        else if (SV == 1) process_tile<M, false, true, BASE_NONE, true, false, TOP>(P, c.D, c.TR, S, c.a, false, true, lw);
-        else process_tile<M, false, true, BASE_Y, true, true, TOP>(P, c.D, c.TR, S, c.a, c.first, true, lw);
+        if (SV == 0) process_tile<M, true, false, BASE_NONE, false, false, TOP, 2>(P, c.D, c.TR, S, c.a, false, true, lw);
+        else if (SV == 1) process_tile<M, false, true, BASE_NONE, true, false, TOP, 2>(P, c.D, c.TR, S, c.a, false, true, lw);
+        else process_tile<M, false, true, BASE_Y, true, true, TOP, 2>(P, c.D, c.TR, S, c.a, c.first, true, lw);
     }
 }
 
@@ -902,11 +937,25 @@ void launch_m(const HostTables &t, hipStream_t s, StageArgs a) {
     // kernel that has no up-move slots, fewer registers and more waves.
     const uint32_t split = (T >= TOP_SPLIT_TILES && t.top_tile > 0 && t.top_tile < T) ? t.top_tile : T;
     a.tile0 = 0;
-    hipLaunchKernelGGL((stage_kernel<M, HAS64, HAS32, BASE, EXTRA, OUT64, false>), dim3(split),
+    // compact tiles have kernels of their own (heom_rhs, the stage without a
+    // base or extra term and with FP64 output, refuses them before this)
+    if constexpr (!(BASE == BASE_NONE && !EXTRA && OUT64)) {
+        if (t.compact) {
+            hipLaunchKernelGGL((stage_kernel<M, HAS64, HAS32, BASE, EXTRA, OUT64, false, 1>), dim3(split),
+                               dim3(t.tile_vars), t.lds_bytes, s, dev_view(t), a, t.tune.xcd_map);
+            if (split < T) {
+                a.tile0 = split;
+                hipLaunchKernelGGL((stage_kernel<M, HAS64, HAS32, BASE, EXTRA, OUT64, true, 1>), dim3(T - split),
+                                   dim3(t.tile_vars), t.lds_bytes, s, dev_view(t), a, t.tune.xcd_map);
+            }
+            return;
+        }
+    }
+    hipLaunchKernelGGL((stage_kernel<M, HAS64, HAS32, BASE, EXTRA, OUT64, false, 0>), dim3(split),
                        dim3(t.tile_vars), t.lds_bytes, s, dev_view(t), a, t.tune.xcd_map);
     if (split < T) {
         a.tile0 = split;
-        hipLaunchKernelGGL((stage_kernel<M, HAS64, HAS32, BASE, EXTRA, OUT64, true>), dim3(T - split),
+        hipLaunchKernelGGL((stage_kernel<M, HAS64, HAS32, BASE, EXTRA, OUT64, true, 0>), dim3(T - split),
                            dim3(t.tile_vars), t.lds_bytes, s, dev_view(t), a, t.tune.xcd_map);
     }
 }
@@ -946,7 +995,10 @@ struct WorkView {
     float2 *u1, *u2, *u3, *u1T, *u2T, *u3T;
     unsigned char *ctrl;
 };
-size_t vec_bytes(const HostTables &t) { return (size_t)t.n_var * (t.trcol ? 80 : 32); }
+// transposed copies exist for tables with transposed column targets that are
+// not compact (compact tables serve Hermitian ADOs only, which need none)
+bool has_copies(const HostTables &t) { return t.trcol && !t.compact; }
+size_t vec_bytes(const HostTables &t) { return (size_t)t.n_var * (has_copies(t) ? 80 : 32); }
 WorkView work_view(const HostTables &t, void *work) {
     const size_t n = t.n_var;
     unsigned char *wb = static_cast<unsigned char *>(work);
@@ -956,7 +1008,7 @@ WorkView work_view(const HostTables &t, void *work) {
     w.u3 = reinterpret_cast<float2 *>(wb);
     w.u1 = reinterpret_cast<float2 *>(wb + 16 * n);
     w.u2 = w.u1 + n;
-    if (t.trcol) {
+    if (has_copies(t)) {
         w.yT = reinterpret_cast<double2 *>(wb + 32 * n);
         w.w0T = w.yT + n;
         w.w1T = w.w0T + n;
@@ -1019,7 +1071,7 @@ int launch_persistent(const HostTables &t, hipStream_t s, const PersistArgs &pa,
 }
 
 size_t work_bytes_for(const HostTables &t) { return vec_bytes(t) + CTRL_BYTES; }
-size_t rhs_work_bytes_for(const HostTables &t) { return t.trcol ? (size_t)t.n_var * 16 : 0; }
+size_t rhs_work_bytes_for(const HostTables &t) { return has_copies(t) ? (size_t)t.n_var * 16 : 0; }
 
 // c_check_k = conj(c_k) for every channel: the condition under which the
 // propagation maps Hermitian ADOs to Hermitian ADOs (Eq. adjoint-preservation).
@@ -1211,7 +1263,11 @@ int heom_table_info(const heom_tables *h, heom_sizes *out) {
     out->hier_gathers = t.hier_gathers;
     out->rhs_work_bytes = (int64_t)rhs_work_bytes_for(t);
     out->transposed = t.trcol ? 1 : 0;
-    out->reserved = 0;
+    out->compact = t.compact ? 1 : 0;
+    size_t covered = 0;
+    for (const TileRec &r : t.tiles) covered += r.nv;
+    out->stage_table_bytes = (int64_t)t.image.size() -
+                             (t.compact ? (int64_t)((sizeof(VarRec) + sizeof(uint16_t)) * (t.n_var - covered)) : 0);
     return HEOM_OK;
 }
 
@@ -1338,6 +1394,7 @@ int heom_rhs(const heom_tables *h, const void *y_dev, void *dy_dev, void *work_d
     if (int rc = check_dev(dy_dev, "dy_dev")) return rc;
     if (y_dev == dy_dev) return fail(HEOM_E_INVAL, "y_dev and dy_dev must differ");
     const HostTables &t = h->t;
+    if (t.compact) return fail(HEOM_E_STATE, "compact tiles serve heom_propagate with HEOM_HERMITIAN only");
     const size_t need = rhs_work_bytes_for(t);
     if (need > 0 && !work_dev) return fail(HEOM_E_INVAL, "work_dev is NULL");
     if (work_bytes < need) return fail(HEOM_E_TOO_LARGE, "work buffer smaller than rhs_work_bytes");
@@ -1380,6 +1437,7 @@ int heom_propagate(const heom_tables *h, void *y_dev, void *work_dev, size_t wor
     if (work_bytes < work_bytes_for(t)) return fail(HEOM_E_TOO_LARGE, "work buffer smaller than work_bytes");
     if (hermitian && !adjoint_preserving(t))
         return fail(HEOM_E_INVAL, "HEOM_HERMITIAN needs c_check = conj(c) for every channel");
+    if (t.compact && !hermitian) return fail(HEOM_E_STATE, "compact tiles need HEOM_HERMITIAN");
     hipStream_t s = static_cast<hipStream_t>(stream);
     double2 *y = static_cast<double2 *>(y_dev);
     if (obs_every > 0) {
@@ -1479,14 +1537,20 @@ int heom_set_tuning(heom_tables *h, const heom_tuning *tu) {
     if (tu->persistent < 0 || tu->persistent > 2) return fail(HEOM_E_INVAL, "persistent must be 0, 1 or 2");
     if (tu->cache_policy < 0 || tu->cache_policy > 7) return fail(HEOM_E_INVAL, "cache_policy must be 0..7");
     if (tu->transposed < -1 || tu->transposed > 1) return fail(HEOM_E_INVAL, "transposed must be -1, 0 or 1");
-    const bool trcol = tu->transposed < 0 ? t.n_var >= TRANSPOSED_MIN_VARS : tu->transposed != 0;
+    if (tu->compact < 0 || tu->compact > 1) return fail(HEOM_E_INVAL, "compact must be 0 or 1");
+    const bool compact = tu->compact != 0;
+    const bool trcol = compact || (tu->transposed < 0 ? t.n_var >= TRANSPOSED_MIN_VARS : tu->transposed != 0);
     const int tv = tu->tile_vars != 0 ? tu->tile_vars : t.tile_vars;
-    const int old_mode = t.tune.transposed;
+    const int old_mode = t.tune.transposed, old_compact = t.tune.compact, old_tv = t.tile_vars;
     t.tune.transposed = tu->transposed;
-    if (tv != t.tile_vars || trcol != t.trcol) {
+    t.tune.compact = tu->compact;
+    if (tv != t.tile_vars || trcol != t.trcol || compact != t.compact) {
         std::string err;
         if (int rc = make_tiles(&t, tv, &err)) {
             t.tune.transposed = old_mode;
+            t.tune.compact = old_compact;
+            // restore the previous tiles (the same arguments built them before)
+            make_tiles(&t, old_tv, &err);
             return fail(rc, err);
         }
     }
@@ -1518,6 +1582,7 @@ int heom_get_tuning(const heom_tables *h, heom_tuning *tu) {
     tu->spin_limit = h->t.tune.spin_limit;
     tu->cache_policy = h->t.tune.cache_policy;
     tu->transposed = h->t.tune.transposed;
+    tu->compact = h->t.tune.compact;
     return HEOM_OK;
 }
 
@@ -1824,6 +1889,9 @@ int heom_batch_propagate(heom_batch *b, int64_t nsteps, int precision, void *str
     if (base_prec != HEOM_FP64 && base_prec != HEOM_FP32) return fail(HEOM_E_INVAL, "unknown precision");
     hipStream_t s = static_cast<hipStream_t>(stream);
     if (nsteps == 0) return HEOM_OK;
+    for (const auto &S : b->slots)
+        if (S.used && S.tables->t.compact && !(precision & HEOM_HERMITIAN))
+            return fail(HEOM_E_STATE, "a slot has compact tiles, which need HEOM_HERMITIAN");
     // slots with transposed copies: the copy of y, made once per call
     // (Hermitian ADOs use no copies)
     for (size_t i = 0; i < b->slots.size(); ++i) {

@@ -75,9 +75,13 @@ HEOM_HD int conn_remap(uint32_t info, int q, int r) {
 
 // One workgroup tile: a run of whole patterns and the contiguous ranges of
 // their variables, categories and hierarchy gather indices. 32 bytes.
+// With compact tiles (Hermitian ADOs) the tile's threads cover only the
+// entries of the upper triangle (row <= column) and the T_q of its blocks:
+// nv counts those, and the decode record and variable index of thread t are
+// at v0 + t of the records and of the compact index list.
 struct TileRec {
     uint32_t p0, np;     // patterns
-    uint32_t v0, nv;     // unique variables
+    uint32_t v0, nv;     // unique variables (compact: the covered entries)
     uint32_t c0, nc;     // category records
     uint32_t g0, ng;     // gather indices (see expand_gathers)
 };
@@ -130,9 +134,12 @@ struct InstParams {
     double cr[HEOM_MAX_M], ci[HEOM_MAX_M];      // c_k
     double ccr[HEOM_MAX_M], cci[HEOM_MAX_M];    // c_check_k
     int32_t m, L, d, n_pat;
-    uint32_t n_var, n_tiles, tile_vars, max_np, max_nc, max_ng, lds_bytes, pad;
+    uint32_t n_var, n_tiles, tile_vars, max_np, max_nc, max_ng, lds_bytes;
+    uint32_t val_len;  // tile values held in LDS: tile_vars, or the largest compact tile's variables
+    uint32_t compact;  // 1: compact tiles (see TileRec)
+    uint32_t tcol;     // 1: column moves name transposed positions
     // byte offsets of the sections from the image base
-    uint64_t off_lut, off_hdr, off_cat, off_gidx, off_tile, off_vrec;
+    uint64_t off_lut, off_hdr, off_cat, off_gidx, off_tile, off_vrec, off_vloc;
 };
 
 struct HostTables {
@@ -151,7 +158,8 @@ struct HostTables {
     std::vector<TileRec> tiles;         // workgroup tiles
     std::vector<uint32_t> gidx;         // per-tile lists of gather target indices
     std::vector<VarRec> vrec;           // per-variable decode records
-    uint32_t max_np = 0, max_nc = 0, max_ng = 0, lds_bytes = 0;
+    std::vector<uint16_t> vloc;         // compact tiles: tile-relative variable of each thread
+    uint32_t max_np = 0, max_nc = 0, max_ng = 0, lds_bytes = 0, val_len = 0;
     std::vector<uint16_t> pat_ids;      // flat: d dist ids + pool ids
     std::vector<uint32_t> pat_start;    // per pattern start in pat_ids, then end
     uint32_t n_var = 0;
@@ -159,8 +167,9 @@ struct HostTables {
     int64_t hier_gathers = 0;
     std::vector<double> lut;            // up[k][n] then dn[k][n]
     std::vector<unsigned char> image;   // device image (host staging)
-    heom_tuning tune{0, 0, 0, 0, 0, 6, -1};  // tile_vars unused here; persistent, xcd_map, max_workgroups, spin_limit, cache_policy, transposed
-    bool trcol = false;                 // column gathers read the transposed copies (resolved from tune.transposed)
+    heom_tuning tune{0, 0, 0, 0, 0, 6, -1, 0};  // tile_vars unused here; persistent, xcd_map, max_workgroups, spin_limit, cache_policy, transposed, compact
+    bool trcol = false;                 // column gathers name transposed positions (tune.transposed, or compact)
+    bool compact = false;               // compact tiles (tune.compact): Hermitian ADOs only
     uint32_t top_tile = 0;              // first tile whose patterns are all in tier L
     void *dev = nullptr;                // uploaded image
     size_t dev_bytes = 0;

@@ -442,6 +442,7 @@ void expand_gathers(const HostTables &t, uint32_t p, std::vector<uint32_t> *out)
             A = B = __builtin_ffs(mask);
             isT = true;
         }
+        if (t.compact && A > B) continue;    // lower triangle: the conjugate of its mirror
         const int kind = (A == 0 && B == 0) ? KIND_Z : (B == 0 ? KIND_X : (A == 0 ? KIND_Y : ((A == B && !isT) ? KIND_P : KIND_S)));
         const int q = A - 1, r = B - 1;
         const CatRec cq = A > 0 ? cats[q] : CatRec{}, cr = B > 0 ? cats[r] : CatRec{};
@@ -468,8 +469,11 @@ void expand_gathers(const HostTables &t, uint32_t p, std::vector<uint32_t> *out)
     }
 }
 
-// Decode records of the variables of one tile, in variable order (VarRec).
-static int var_records(const HostTables &t, const TileRec &r, std::vector<VarRec> *out) {
+// Decode records of the variables of one tile, in variable order (VarRec);
+// for compact tiles only the entries with row <= column and the T_q, each
+// with its tile-relative variable in *loc_out.
+static int var_records(const HostTables &t, const TileRec &r, std::vector<VarRec> *out,
+                       std::vector<uint16_t> *loc_out) {
     const int M = t.m;
     uint32_t goff = 0;
     for (uint32_t pi = 0; pi < r.np; ++pi) {
@@ -489,11 +493,13 @@ static int var_records(const HostTables &t, const TileRec &r, std::vector<VarRec
                 A = B = __builtin_ffs(mask);
                 isT = true;
             }
+            if (t.compact && A > B) continue;
             const int kind = (A == 0 && B == 0) ? KIND_Z : (B == 0 ? KIND_X : (A == 0 ? KIND_Y : ((A == B && !isT) ? KIND_P : KIND_S)));
             const CatRec cq = A > 0 ? cats[A - 1] : CatRec{}, cr = B > 0 ? cats[B - 1] : CatRec{};
             const uint32_t live = live_slots(kind, chi, cq.vec, cr.vec, M);
             if (goff > VREC_MAX_GOFF) return HEOM_E_UNSUPPORTED;
             out->push_back(vrec_pack(pi, (uint32_t)A, (uint32_t)B, isT, goff, live));
+            if (t.compact) loc_out->push_back((uint16_t)(H.off - r.v0 + loc));
             goff += (uint32_t)__builtin_popcount(live);
         }
     }
@@ -512,22 +518,38 @@ int make_tiles(HostTables *t, int tile_vars, std::string *err) {
         return HEOM_E_INVAL;
     }
     t->tile_vars = tile_vars;
-    t->trcol = t->tune.transposed < 0 ? t->n_var >= TRANSPOSED_MIN_VARS : t->tune.transposed != 0;
+    t->compact = t->tune.compact != 0;
+    t->trcol = t->compact || (t->tune.transposed < 0 ? t->n_var >= TRANSPOSED_MIN_VARS : t->tune.transposed != 0);
     t->tiles.clear();
     const size_t np = t->hdr.size();
     size_t i = 0;
     t->max_np = t->max_nc = t->max_ng = 0;
+    t->val_len = t->compact ? 0u : (uint32_t)tile_vars;
     t->gidx.clear();
     t->vrec.clear();
+    t->vloc.clear();
     t->vrec.reserve(t->n_var);
+    // entries a compact tile covers in a block: row <= column, and the T_q
+    auto covered = [](const PatHdr &h) { return (uint32_t)(h.G + 1) * (uint32_t)(h.G + 2) / 2u + (h.size - (uint32_t)(h.G + 1) * (uint32_t)(h.G + 1)); };
     while (i < np) {
         TileRec r{};
         r.p0 = (uint32_t)i;
         r.v0 = t->hdr[i].off;
-        uint32_t acc = 0;
-        while (i < np && acc + t->hdr[i].size <= (uint32_t)tile_vars) acc += t->hdr[i++].size;
+        uint32_t acc = 0, work = 0;
+        if (t->compact) {
+            // up to tile_vars covered entries and 2 tile_vars variables (the LDS values)
+            while (i < np && work + covered(t->hdr[i]) <= (uint32_t)tile_vars &&
+                   acc + t->hdr[i].size <= 2u * (uint32_t)tile_vars && i - r.p0 < VREC_MAX_NP) {
+                acc += t->hdr[i].size;
+                work += covered(t->hdr[i++]);
+            }
+        } else {
+            while (i < np && acc + t->hdr[i].size <= (uint32_t)tile_vars) acc += t->hdr[i++].size;
+            work = acc;
+        }
         r.np = (uint32_t)i - r.p0;
-        r.nv = acc;
+        r.nv = work;
+        if (t->compact) t->val_len = std::max(t->val_len, acc);
         r.c0 = t->hdr[r.p0].cat_base;
         r.nc = (i < np ? t->hdr[i].cat_base : (uint32_t)t->cat.size()) - r.c0;
         r.g0 = (uint32_t)t->gidx.size();
@@ -538,7 +560,12 @@ int make_tiles(HostTables *t, int tile_vars, std::string *err) {
             *err = "a tile has more patterns or hierarchy gathers than its records can address";
             return HEOM_E_UNSUPPORTED;
         }
-        if (int rc = var_records(*t, r, &t->vrec)) { *err = "variable records do not match the gather lists"; return rc; }
+        // compact tables keep one record slot per variable (v0 + thread)
+        if (t->compact) {
+            t->vrec.resize(r.v0);
+            t->vloc.resize(r.v0);
+        }
+        if (int rc = var_records(*t, r, &t->vrec, &t->vloc)) { *err = "variable records do not match the gather lists"; return rc; }
         // each tile's list starts on a 16-byte boundary (staged as 16-byte words)
         while (t->gidx.size() % 4) t->gidx.push_back(0u);
         t->max_np = std::max(t->max_np, r.np);
@@ -546,12 +573,16 @@ int make_tiles(HostTables *t, int tile_vars, std::string *err) {
         t->max_ng = std::max(t->max_ng, r.ng);
         t->tiles.push_back(r);
     }
+    if (t->compact) {
+        t->vrec.resize(t->n_var);
+        t->vloc.resize(t->n_var);
+    }
     t->top_tile = (uint32_t)t->tiles.size();
     for (size_t k = 0; k < t->tiles.size(); ++k)
         if (t->hdr[t->tiles[k].p0].tier == t->L) { t->top_tile = (uint32_t)k; break; }
     // LDS per workgroup: values, grouped sums, pattern headers, categories,
     // gather indices, coefficient tables, category multiplicities (FP64)
-    t->lds_bytes = 32u * tile_vars + 32u * t->max_np + 16u * t->max_nc + 4u * ((t->max_ng + 3u) & ~3u) +
+    t->lds_bytes = 32u * t->val_len + 32u * t->max_np + 16u * t->max_nc + 4u * ((t->max_ng + 3u) & ~3u) +
                    16u * (uint32_t)t->m * (uint32_t)(t->L + 1) + 8u * t->max_nc;
     if (t->lds_bytes > 64u * 1024u) {
         *err = "tile needs more than 64 KiB of LDS";
@@ -613,19 +644,23 @@ static InstParams make_params(const HostTables &num, const HostTables &st) {
     ip.max_nc = st.max_nc;
     ip.max_ng = st.max_ng;
     ip.lds_bytes = st.lds_bytes;
+    ip.val_len = st.val_len;
+    ip.compact = st.compact ? 1u : 0u;
+    ip.tcol = st.trcol ? 1u : 0u;
     size_t o = align256(sizeof(InstParams));
     ip.off_lut = o;   o = align256(o + st.lut.size() * sizeof(double));
     ip.off_hdr = o;   o = align256(o + st.hdr.size() * sizeof(PatHdr));
     ip.off_cat = o;   o = align256(o + st.cat.size() * sizeof(CatRec));
     ip.off_gidx = o;  o = align256(o + st.gidx.size() * sizeof(uint32_t));
     ip.off_tile = o;  o = align256(o + st.tiles.size() * sizeof(TileRec));
-    ip.off_vrec = o;
+    ip.off_vrec = o;  o = align256(o + st.vrec.size() * sizeof(VarRec));
+    ip.off_vloc = o;
     return ip;
 }
 
 size_t image_bytes(const HostTables &t) {
     const InstParams ip = make_params(t, t);
-    return align256(ip.off_vrec + t.vrec.size() * sizeof(VarRec));
+    return align256(ip.off_vloc + t.vloc.size() * sizeof(uint16_t));
 }
 
 int pack_params(const HostTables &t, const heom_problem *p, std::vector<unsigned char> *out, std::string *err) {
@@ -661,6 +696,8 @@ void pack_image(HostTables *t) {
     std::memcpy(t->image.data() + ip.off_gidx, t->gidx.data(), t->gidx.size() * sizeof(uint32_t));
     std::memcpy(t->image.data() + ip.off_tile, t->tiles.data(), t->tiles.size() * sizeof(TileRec));
     std::memcpy(t->image.data() + ip.off_vrec, t->vrec.data(), t->vrec.size() * sizeof(VarRec));
+    if (!t->vloc.empty())
+        std::memcpy(t->image.data() + ip.off_vloc, t->vloc.data(), t->vloc.size() * sizeof(uint16_t));
 }
 
 }  // namespace heom

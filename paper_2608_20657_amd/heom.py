@@ -54,7 +54,7 @@ class _Problem(ctypes.Structure):
 class _Tuning(ctypes.Structure):
     _fields_ = [("tile_vars", ctypes.c_int32), ("persistent", ctypes.c_int32), ("xcd_map", ctypes.c_int32),
                 ("max_workgroups", ctypes.c_int32), ("spin_limit", ctypes.c_int32),
-                ("cache_policy", ctypes.c_int32), ("transposed", ctypes.c_int32)]
+                ("cache_policy", ctypes.c_int32), ("transposed", ctypes.c_int32), ("compact", ctypes.c_int32)]
 
 
 class _Sizes(ctypes.Structure):
@@ -63,7 +63,8 @@ class _Sizes(ctypes.Structure):
                 ("table_bytes", ctypes.c_int64), ("work_bytes_fp64", ctypes.c_int64),
                 ("work_bytes_fp32", ctypes.c_int64), ("tier0_size", ctypes.c_int64),
                 ("max_G", ctypes.c_int32), ("tile_vars", ctypes.c_int32), ("hier_gathers", ctypes.c_int64),
-                ("rhs_work_bytes", ctypes.c_int64), ("transposed", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("rhs_work_bytes", ctypes.c_int64), ("transposed", ctypes.c_int32), ("compact", ctypes.c_int32),
+                ("stage_table_bytes", ctypes.c_int64)]
 
 
 def _load():
@@ -264,8 +265,9 @@ class Tables:
 
     def set_tuning(self, **kw):
         """Change launch knobs (tile_vars, persistent, xcd_map, max_workgroups,
-        spin_limit, cache_policy, transposed). A new tile_vars or a change of
-        the transposed copies needs a new upload() and new work sizes."""
+        spin_limit, cache_policy, transposed, compact). A new tile_vars or a
+        change of the transposed copies or compact tiles needs a new upload()
+        and new work sizes."""
         cur = self.tuning()
         cur["tile_vars"] = 0
         cur.update(kw)

@@ -214,7 +214,8 @@ class Server:
     len(lanes)+1 lanes. capacity: slots per lane (an int or one per lane).
     precision: HEOM_FP64 or HEOM_FP32 (FP32 bulk with FP64 state), with
     HEOM_HERMITIAN OR-ed in when every request's ADOs are Hermitian (a
-    Hermitian rho_S(0) and c_check = conj(c)).
+    Hermitian rho_S(0) and c_check = conj(c)); the structures then use
+    compact tiles (heom_tuning.compact).
     target_ms: device time per chunk; sets how long an arrival waits for
     its lane's next chunk boundary."""
 
@@ -255,7 +256,10 @@ class Server:
         key = structure_key(p)
         s = self.structs.get(key)
         if s is None:
-            s = _Structure(heom.Tables(p))
+            T = heom.Tables(p)
+            if self.precision & heom.HEOM_HERMITIAN:
+                T.set_tuning(compact=1)
+            s = _Structure(T)
             self.structs[key] = s
         return s
 
@@ -488,6 +492,8 @@ class Fifo:
         T = self.structs.get(key)
         if T is None:
             T = heom.Tables(p)
+            if self.precision & heom.HEOM_HERMITIAN:
+                T.set_tuning(compact=1)
             self.structs[key] = T
         return T
 

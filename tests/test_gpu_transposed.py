@@ -194,3 +194,99 @@ def test_batch_hermitian_equals_solo():
         for (T, y, work, obs), (wy, wo) in zip(keep, want):
             assert np.array_equal(y.cpu().numpy().view(np.float64), wy.view(np.float64))
             assert np.array_equal(obs.cpu().numpy().reshape(-1, 10), wo)
+
+
+# Compact tiles (heom_tuning.compact): threads cover only each block's upper
+# triangle and T_q, write the mirrored entry as the conjugate, and take the
+# column sums as conjugates of the row sums. Hermitian ADOs only.
+def compact_tables(p, tile_vars=0):
+    torch = torch_cuda()
+    from paper_2608_20657_amd import heom
+    T = heom.Tables(p)
+    kw = {"compact": 1}
+    if tile_vars:
+        kw["tile_vars"] = tile_vars
+    T.set_tuning(**kw)
+    info = T.info()
+    assert info["compact"] == 1 and info["transposed"] == 1 and info["rhs_work_bytes"] == 0
+    buf = torch.empty(info["table_bytes"], dtype=torch.uint8, device="cuda")
+    T.upload(buf, torch.cuda.current_stream())
+    return T, torch
+
+
+@pytest.mark.parametrize("tile_vars", [64, 256])
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("N,m,L,d,state", HERM)
+def test_compact_matches_general(N, m, L, d, state, precision, tile_vars):
+    from paper_2608_20657_amd import heom
+    p = herm_problem(N, m, L, d)
+    Tg, torch = tables(p, 0, tile_vars=64)
+    Tc, _ = compact_tables(p, tile_vars=tile_vars)
+    t0 = named_tier0(Tg, p, state)
+    yg, og = gpu_propagate(Tg, torch, t0, 0.05, 23, 5, precision)
+    yc, oc = gpu_propagate(Tc, torch, t0, 0.05, 23, 5, precision | heom.HEOM_HERMITIAN)
+    tol = 1e-12 if precision == 0 else 1e-6
+    assert np.abs(yc - yg).max() <= tol * np.abs(yg).max()
+    assert np.abs(oc - og).max() <= tol * max(1.0, np.abs(og).max())
+
+
+def test_compact_large_state():
+    from paper_2608_20657_amd import heom
+    p = W.random_problem(100, 4, 8, 0, seed=3)
+    Tc, torch = compact_tables(p)
+    Tg, _ = tables(p, 0)
+    t0 = named_tier0(Tg, p, "photon")
+    for precision in (0, 1):
+        yg, og = gpu_propagate(Tg, torch, t0, 0.02, 6, 3, precision)
+        yc, oc = gpu_propagate(Tc, torch, t0, 0.02, 6, 3, precision | heom.HEOM_HERMITIAN)
+        tol = 1e-12 if precision == 0 else 1e-6
+        assert np.abs(yc - yg).max() <= tol * np.abs(yg).max()
+        assert np.abs(oc - og).max() <= tol
+
+
+def test_compact_needs_hermitian_flag():
+    from paper_2608_20657_amd import heom
+    p = herm_problem(5, 2, 3, 1)
+    Tc, torch = compact_tables(p, tile_vars=64)
+    t0 = named_tier0(Tc, p, "site1")
+    with pytest.raises(heom.HeomError) as e:
+        gpu_propagate(Tc, torch, t0, 0.05, 3, 1, 0)
+    assert e.value.code == -7
+    with pytest.raises(heom.HeomError) as e:
+        gpu_rhs(Tc, torch, W.random_vector(Tc.info()["n_var"], seed=1))
+    assert e.value.code == -7
+
+
+def test_batch_compact_equals_solo():
+    """Compact and full slots in one batch, Hermitian flag: each slot equals
+    its own heom_propagate run, bitwise."""
+    from paper_2608_20657_amd import heom
+    torch = torch_cuda()
+    s = torch.cuda.current_stream()
+    probs = [(5, 2, 3, 1, "site1", "compact"), (7, 3, 3, 0, "photon", "full"),
+             (64, 2, 6, 1, "site1", "compact"), (6, 5, 2, 0, "photon", "transposed")]
+    steps, every, dt = 17, 4, 0.05
+    for precision in (0, 1):
+        flag = precision | heom.HEOM_HERMITIAN
+        b = heom.Batch(len(probs))
+        keep, want = [], []
+        for i, (N, m, L, d, state, kind) in enumerate(probs):
+            p = herm_problem(N, m, L, d)
+            T, _ = compact_tables(p, 64) if kind == "compact" else tables(p, 1 if kind == "transposed" else 0, 64)
+            t0 = named_tier0(T, p, state)
+            want.append(gpu_propagate(T, torch, t0, dt, steps, every, flag))
+            info = T.info()
+            y = torch.empty(info["n_var"], dtype=torch.complex128, device="cuda")
+            T.init_state(t0, y, s)
+            work = torch.empty(info["work_bytes_fp64"], dtype=torch.uint8, device="cuda")
+            obs = torch.zeros((steps // every + 1) * 10, dtype=torch.float64, device="cuda")
+            b.set_slot(i, T, y, work, dt, obs=obs, obs_every=every)
+            keep.append((T, y, work, obs))
+        b.commit(torch, s)
+        with pytest.raises(heom.HeomError):
+            b.propagate(1, precision, s)        # compact slots need the flag
+        b.propagate(steps, flag, s)
+        torch.cuda.synchronize()
+        for (T, y, work, obs), (wy, wo) in zip(keep, want):
+            assert np.array_equal(y.cpu().numpy().view(np.float64), wy.view(np.float64))
+            assert np.array_equal(obs.cpu().numpy().reshape(-1, 10), wo)

@@ -175,3 +175,21 @@ def test_transposed_copies_sizes_and_knob():
     with pytest.raises(heom.HeomError):
         T.set_tuning(transposed=2)
     assert T.tuning()["transposed"] == -1
+
+
+def test_compact_tiles_sizes_and_knob():
+    """Compact tiles: transposed column targets without copies (work stays
+    32 bytes per variable), plus a 2-byte variable index per variable."""
+    p = W.random_problem(6, 3, 3, 1, seed=4)
+    T = heom.Tables(p)
+    i0 = T.info()
+    T.set_tuning(compact=1)
+    i1 = T.info()
+    assert i1["compact"] == 1 and i1["transposed"] == 1 and i1["rhs_work_bytes"] == 0
+    assert i1["work_bytes_fp64"] == i0["work_bytes_fp64"]
+    assert i1["n_tiles"] <= i0["n_tiles"]
+    assert T.tuning()["compact"] == 1
+    T.set_tuning(compact=0)
+    assert T.info()["compact"] == 0 and T.info()["table_bytes"] == i0["table_bytes"]
+    with pytest.raises(heom.HeomError):
+        T.set_tuning(compact=2)
