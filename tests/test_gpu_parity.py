@@ -23,7 +23,7 @@ import pytest
 
 from oracle import conventional, integrate, observables as O, uvar
 from paper_2608_20657_amd import workloads as W
-from tests.gpu_util import gpu_propagate, gpu_rhs, named_tier0, rhs_bound, upload
+from tests.gpu_util import gpu_propagate, gpu_rhs, named_tier0, rhs_bound, torch_cuda, upload
 
 pytestmark = pytest.mark.gpu
 
@@ -325,3 +325,30 @@ def test_barrier_timeout_is_reported():
     assert e.value.code == -8
     T.set_tuning(spin_limit=0)
     gpu_propagate(T, torch, t0, 0.02, 50, 10)     # the flag is cleared per launch
+
+
+def upload_compact(p):
+    """Tables with compact tiles (Hermitian ADOs), uploaded."""
+    torch = torch_cuda()
+    from paper_2608_20657_amd import heom
+    T = heom.Tables(p)
+    T.set_tuning(compact=1)
+    buf = torch.empty(T.info()["table_bytes"], dtype=torch.uint8, device="cuda")
+    T.upload(buf, torch.cuda.current_stream())
+    return T, torch
+
+
+@pytest.mark.parametrize("name", GOLDEN_RUNS)
+def test_propagate_compact_hermitian_vs_golden(name):
+    """Every golden run starts from a Hermitian rho_S(0) with c_check = conj(c):
+    compact tiles under HEOM_HERMITIAN against the oracle's trajectories, FP64
+    and FP32 increments, same bounds as the general path."""
+    from paper_2608_20657_amd import heom
+    g = _golden(name)
+    p, T, torch, t0 = _problem_and_tier0(name, upload_compact, g["state"])
+    ref = np.array(g["observables"])
+    _, obs = gpu_propagate(T, torch, t0, g["dt"], g["steps"], g["every"], precision=heom.HEOM_HERMITIAN)
+    for j in range(9):
+        assert np.abs(obs[:, j] - ref[:, j]).max() <= 1e-10 * max(np.abs(ref[:, j]).max(), 1e-300), j
+    _, obs = gpu_propagate(T, torch, t0, g["dt"], g["steps"], g["every"], precision=1 | heom.HEOM_HERMITIAN)
+    assert np.abs(obs[:, 1:9] - ref[:, 1:9]).max() <= 1e-5
