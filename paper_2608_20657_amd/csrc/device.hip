@@ -539,20 +539,13 @@ __device__ __forceinline__ void process_tile(const InstParams &P, const Dev &D, 
         res = cscale(a.alpha, acc);
         if (BASE == BASE_IN) res = cadd(res, own);
         if (BASE == BASE_Y) res = cadd(res, ybv);
-        const double2 rc = make_double2(res.x, -res.y);
-        if (a.policy & 4u) {
-            if (OUT64) st_stream(a.out64 + TR.v0 + vt, res);
-            else st_stream(a.out32 + TR.v0 + vt, res);
-            if (has_mirror) {
-                if (OUT64) st_stream(a.out64 + TR.v0 + vmir, rc);
-                else st_stream(a.out32 + TR.v0 + vmir, rc);
-            }
-        } else {
-            if (OUT64) a.out64[TR.v0 + vt] = res;
-            else a.out32[TR.v0 + vt] = make_float2((float)res.x, (float)res.y);
-            if (has_mirror) {
-                if (OUT64) a.out64[TR.v0 + vmir] = rc;
-                else a.out32[TR.v0 + vmir] = make_float2((float)rc.x, (float)rc.y);
+        if (!cmp) {
+            if (a.policy & 4u) {
+                if (OUT64) st_stream(a.out64 + TR.v0 + vt, res);
+                else st_stream(a.out32 + TR.v0 + vt, res);
+            } else {
+                if (OUT64) a.out64[TR.v0 + vt] = res;
+                else a.out32[TR.v0 + vt] = make_float2((float)res.x, (float)res.y);
             }
         }
         if (OUT64 ? a.outT64 != nullptr : a.outT32 != nullptr) {
@@ -568,14 +561,34 @@ __device__ __forceinline__ void process_tile(const InstParams &P, const Dev &D, 
         }
     }
     __syncthreads();
-    if (a.obs != nullptr && first_tile) {
-        // the empty pattern is the first block of tile 0: evaluate the
-        // observables of the freshly computed tier-0 block
-        const uint32_t n0 = S.hdr[0].size;
-        if (active && vt < n0) {
+    if (cmp) {
+        // compact tiles: the results and their mirrors are gathered in LDS
+        // first, so that the tile's variables are stored as one contiguous
+        // run of whole lines (scattered mirror stores leave partial lines)
+        if (active) {
             S.val[vt] = res;
             if (has_mirror) S.val[vmir] = make_double2(res.x, -res.y);
         }
+        __syncthreads();
+        const PatHdr HL = S.hdr[TR.np - 1];
+        const uint32_t nfull = HL.off + HL.size - TR.v0;
+        for (uint32_t i = t; i < nfull; i += blockDim.x) {
+            const double2 r = S.val[i];
+            if (a.policy & 4u) {
+                if (OUT64) st_stream(a.out64 + TR.v0 + i, r);
+                else st_stream(a.out32 + TR.v0 + i, r);
+            } else {
+                if (OUT64) a.out64[TR.v0 + i] = r;
+                else a.out32[TR.v0 + i] = make_float2((float)r.x, (float)r.y);
+            }
+        }
+    }
+    if (a.obs != nullptr && first_tile) {
+        // the empty pattern is the first block of tile 0: evaluate the
+        // observables of the freshly computed tier-0 block (compact tiles
+        // hold it in LDS already)
+        const uint32_t n0 = S.hdr[0].size;
+        if (!cmp && active && vt < n0) S.val[vt] = res;
         __syncthreads();
         if (t == 0) tier0_observables(P, S.hdr[0], S.cat, S.val, a.obs);
         __syncthreads();
