@@ -354,6 +354,11 @@ __device__ __forceinline__ double2 load_own(const StageArgs &a, uint32_t j) {
 //    so the loop body has no branches.
 // 4. Every thread reads its Hamiltonian bracket from LDS, adds damping,
 //    loss, the terminator and the extra term, and writes the combination.
+// Compact tiles (Hermitian ADOs) cover only the entries with row <= column
+// and the T_q: a thread also fills its mirrored entry (the conjugate) into
+// LDS, the grouped sums are the Z bracket and the row sums (the column sums
+// are their conjugates), and the results go through LDS so that the tile's
+// variables are stored as one contiguous run.
 template <int M, bool HAS64, bool HAS32, int BASE, bool EXTRA, bool OUT64, bool TOP, int CM>
 __device__ __forceinline__ void process_tile(const InstParams &P, const Dev &D, const TileRec &TR, const Smem &S,
                                              const StageArgs &a, bool first_tile, bool stage, uint32_t lut_w) {
