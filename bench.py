@@ -431,6 +431,20 @@ def main():
             "table_build_s": round(build_s, 2),
         }
         del ry, img2, TR
+        if herm and not args.roofline_only:
+            # the same stage on the general path (no Hermitian assertion: full
+            # tiles, column gathers from a transposed copy), for reference
+            TG = heom.Tables(q)
+            img3 = torch.empty(TG.info()["table_bytes"], dtype=torch.uint8, device="cuda")
+            TG.upload(img3, torch.cuda.current_stream())
+            gms, _, gy, _ = time_propagate(TG, torch, t0r, dt, 10, 3, 0, 0)
+            gl = gms / 40.0
+            gbytes = ri["n_var"] * stage_bytes_per_var(0) / 4.0 + TG.info()["stage_table_bytes"]
+            out["roofline"]["general_path"] = {
+                "mean_launch_us": round(gl * 1e3, 2), "algorithmic_bytes_per_launch": int(gbytes),
+                "achieved": round(gbytes / (gl * 1e-3) / 1e9, 1),
+                "frac": round(gbytes / (gl * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+            del gy, img3, TG
 
     if args.roofline_only:
         args.no_batched = args.no_serve = True
