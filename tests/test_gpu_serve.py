@@ -118,3 +118,25 @@ def test_rejects_what_cannot_fit():
     srv = S.Server(torch, 4096)
     st = srv.run(reqs)
     assert st["completed"] == 0 and st["rejected"] == 2
+
+
+def test_served_hermitian_compact_equals_fifo_and_matches_general():
+    """Under HEOM_HERMITIAN the server and the FIFO build compact tiles; the
+    requests (Hermitian rho_S(0), c_check = conj(c)) then agree bitwise
+    between served and plain, and with the general path to rounding."""
+    torch = torch_cuda()
+    from paper_2608_20657_amd import heom, serve as S
+    reqs = requests()
+    herm = heom.HEOM_HERMITIAN
+    res_h, st, srv = run_server(reqs, herm)
+    assert st["completed"] == len(reqs)
+    assert all(s.tables.info()["compact"] == 1 for s in srv.structs.values())
+    fifo = S.Fifo(torch, precision=herm, chunk=40)
+    fifo.prepare([r.problem for r in reqs])
+    assert fifo.run(reqs)["completed"] == len(reqs)
+    for r in fifo.results:
+        assert np.array_equal(r.obs, res_h[r.rid].obs), f"request {r.rid}: served != plain"
+    res_g, _, _ = run_server(reqs, 0)
+    for r in reqs:
+        a, b = res_g[r.rid].obs, res_h[r.rid].obs
+        assert np.abs(a - b).max() <= 1e-12 * max(1.0, np.abs(a).max())
