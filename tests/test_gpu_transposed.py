@@ -290,3 +290,29 @@ def test_batch_compact_equals_solo():
         for (T, y, work, obs), (wy, wo) in zip(keep, want):
             assert np.array_equal(y.cpu().numpy().view(np.float64), wy.view(np.float64))
             assert np.array_equal(obs.cpu().numpy().reshape(-1, 10), wo)
+
+
+def test_compact_probe_size_matches_general():
+    """At the roofline probe's full size (17.3 M variables): from a Hermitian
+    state with every tier populated (3 general steps from the photon), two
+    more steps on compact tiles under HEOM_HERMITIAN equal two general steps
+    to rounding, entry by entry."""
+    from paper_2608_20657_amd import heom
+    torch = torch_cuda()
+    s = torch.cuda.current_stream()
+    p = W.config_roofline_probe()
+    Tg, _ = tables(p, -1)
+    Tc, _ = compact_tables(p)
+    n = Tg.info()["n_var"]
+    y0 = torch.empty(n, dtype=torch.complex128, device="cuda")
+    Tg.init_state(Tg.tier0_pure(1.0, 0.0, []), y0, s)
+    wg = torch.empty(Tg.info()["work_bytes_fp64"], dtype=torch.uint8, device="cuda")
+    Tg.propagate(y0, wg, 0.02, 3, 0, None, 0, s)
+    yg, yc = y0.clone(), y0.clone()
+    wc = torch.empty(Tc.info()["work_bytes_fp64"], dtype=torch.uint8, device="cuda")
+    Tg.propagate(yg, wg, 0.02, 2, 0, None, 0, s)
+    Tc.propagate(yc, wc, 0.02, 2, 0, None, heom.HEOM_HERMITIAN, s)
+    torch.cuda.synchronize()
+    assert bool(torch.isfinite(yg).all()) and float(yg.abs().max()) > 0
+    err = float((yc - yg).abs().max())
+    assert err <= 1e-12 * float(yg.abs().max()), err
