@@ -241,8 +241,9 @@ struct StageArgs {
 
 enum { BASE_NONE = 0, BASE_IN = 1, BASE_Y = 2 };
 
-// LDS carve-up of one workgroup: tile values, pattern headers, categories,
-// connection records, coefficient tables, category multiplicities.
+// LDS carve-up of one workgroup: tile values and grouped sums, pattern headers,
+// categories, coefficient tables, category multiplicities, gather indices (last,
+// so that a launch whose tiles have shorter lists can allocate less).
 struct Smem {
     double2 *val;
     double2 *rc;      // grouped sums of the tile's blocks (see process_tile)
@@ -259,9 +260,9 @@ __device__ __forceinline__ Smem carve(unsigned char *smem, const InstParams &P) 
     S.rc = S.val + P.val_len;
     S.hdr = reinterpret_cast<PatHdr *>(smem + 32u * P.val_len);
     S.cat = reinterpret_cast<CatRec *>(S.hdr + P.max_np);
-    S.gix = reinterpret_cast<uint32_t *>(S.cat + P.max_nc);
-    S.lut = reinterpret_cast<double *>(S.gix + ((P.max_ng + 3u) & ~3u));
+    S.lut = reinterpret_cast<double *>(S.cat + P.max_nc);
     S.md = S.lut + 2u * (uint32_t)P.m * (uint32_t)(P.L + 1);
+    S.gix = reinterpret_cast<uint32_t *>(S.md + ((P.max_nc + 1u) & ~1u));
     return S;
 }
 
@@ -960,21 +961,22 @@ void launch_m(const HostTables &t, hipStream_t s, StageArgs a) {
     if constexpr (!(BASE == BASE_NONE && !EXTRA && OUT64)) {
         if (t.compact) {
             hipLaunchKernelGGL((stage_kernel<M, HAS64, HAS32, BASE, EXTRA, OUT64, false, 1>), dim3(split),
-                               dim3(t.tile_vars), t.lds_bytes, s, dev_view(t), a, t.tune.xcd_map);
+                               dim3(t.tile_vars), split < T ? t.lds_low : t.lds_bytes, s, dev_view(t), a,
+                               t.tune.xcd_map);
             if (split < T) {
                 a.tile0 = split;
                 hipLaunchKernelGGL((stage_kernel<M, HAS64, HAS32, BASE, EXTRA, OUT64, true, 1>), dim3(T - split),
-                                   dim3(t.tile_vars), t.lds_bytes, s, dev_view(t), a, t.tune.xcd_map);
+                                   dim3(t.tile_vars), t.lds_top, s, dev_view(t), a, t.tune.xcd_map);
             }
             return;
         }
     }
     hipLaunchKernelGGL((stage_kernel<M, HAS64, HAS32, BASE, EXTRA, OUT64, false, 0>), dim3(split),
-                       dim3(t.tile_vars), t.lds_bytes, s, dev_view(t), a, t.tune.xcd_map);
+                       dim3(t.tile_vars), split < T ? t.lds_low : t.lds_bytes, s, dev_view(t), a, t.tune.xcd_map);
     if (split < T) {
         a.tile0 = split;
         hipLaunchKernelGGL((stage_kernel<M, HAS64, HAS32, BASE, EXTRA, OUT64, true, 0>), dim3(T - split),
-                           dim3(t.tile_vars), t.lds_bytes, s, dev_view(t), a, t.tune.xcd_map);
+                           dim3(t.tile_vars), t.lds_top, s, dev_view(t), a, t.tune.xcd_map);
     }
 }
 

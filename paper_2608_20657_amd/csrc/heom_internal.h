@@ -160,6 +160,7 @@ struct HostTables {
     std::vector<VarRec> vrec;           // per-variable decode records
     std::vector<uint16_t> vloc;         // compact tiles: tile-relative variable of each thread
     uint32_t max_np = 0, max_nc = 0, max_ng = 0, lds_bytes = 0, val_len = 0;
+    uint32_t lds_low = 0, lds_top = 0;      // LDS of a launch over the tiles below / in the top tier
     std::vector<uint16_t> pat_ids;      // flat: d dist ids + pool ids
     std::vector<uint32_t> pat_start;    // per pattern start in pat_ids, then end
     uint32_t n_var = 0;

@@ -581,9 +581,20 @@ int make_tiles(HostTables *t, int tile_vars, std::string *err) {
     for (size_t k = 0; k < t->tiles.size(); ++k)
         if (t->hdr[t->tiles[k].p0].tier == t->L) { t->top_tile = (uint32_t)k; break; }
     // LDS per workgroup: values, grouped sums, pattern headers, categories,
-    // gather indices, coefficient tables, category multiplicities (FP64)
-    t->lds_bytes = 32u * t->val_len + 32u * t->max_np + 16u * t->max_nc + 4u * ((t->max_ng + 3u) & ~3u) +
-                   16u * (uint32_t)t->m * (uint32_t)(t->L + 1) + 8u * t->max_nc;
+    // coefficient tables, category multiplicities (FP64, padded to 16 bytes),
+    // then the gather indices. The gather list is last so that a launch over
+    // tiles with shorter lists can allocate less (the top tier's lists, which
+    // have no up moves, are about a third as long).
+    const uint32_t lds_fixed = 32u * t->val_len + 32u * t->max_np + 16u * t->max_nc +
+                               16u * (uint32_t)t->m * (uint32_t)(t->L + 1) + 8u * ((t->max_nc + 1u) & ~1u);
+    uint32_t ng_low = 0, ng_top = 0;
+    for (size_t k = 0; k < t->tiles.size(); ++k) {
+        uint32_t &ng = k < t->top_tile ? ng_low : ng_top;
+        ng = std::max(ng, t->tiles[k].ng);
+    }
+    t->lds_bytes = lds_fixed + 4u * ((t->max_ng + 3u) & ~3u);
+    t->lds_low = lds_fixed + 4u * ((ng_low + 3u) & ~3u);
+    t->lds_top = lds_fixed + 4u * ((ng_top + 3u) & ~3u);
     if (t->lds_bytes > 64u * 1024u) {
         *err = "tile needs more than 64 KiB of LDS";
         return HEOM_E_UNSUPPORTED;

@@ -3,7 +3,8 @@
 // records and gather indices stay in bounds; with compact tiles every
 // variable of a tile is either a covered entry (row <= column, or a T_q) or
 // the mirror of exactly one covered entry; with transposed targets a column
-// move names the mirrored position of the entry a plain table names.
+// move names the mirrored position of the entry a plain table names; every
+// tile's metadata fits the LDS its launch allocates.
 // Prints "ok" and exits 0, or names the first failure and exits 1.
 #include <cstdio>
 #include <cstdlib>
@@ -71,6 +72,18 @@ static int check(int64_t N, int m, int L, int d, int tv) {
                 if (plain.gidx[g] >= plain.n_var) return fail("gather index", g, plain.gidx[g]);
             }
         }
+    // LDS: the gather list is the last section of a workgroup's LDS, so a
+    // tile's list must fit what its launch allocates (lower tiers / top tier)
+    for (const HostTables *T : {&plain, &trans, &comp}) {
+        const uint32_t fixed = T->lds_bytes - 4u * ((T->max_ng + 3u) & ~3u);
+        if (T->lds_low > T->lds_bytes || T->lds_top > T->lds_bytes) return fail("launch LDS", T->lds_low, T->lds_top);
+        for (size_t k = 0; k < T->tiles.size(); ++k) {
+            const TileRec &R = T->tiles[k];
+            const uint32_t alloc = k < T->top_tile ? T->lds_low : T->lds_top;
+            if (R.np > T->max_np || R.nc > T->max_nc || fixed + 4u * ((R.ng + 3u) & ~3u) > alloc)
+                return fail("tile LDS", (long long)k, R.ng);
+        }
+    }
     // compact tiles: coverage, bounds
     std::vector<int> cover(comp.n_var, 0);
     for (const TileRec &R : comp.tiles) {
