@@ -309,8 +309,8 @@ def main():
                     help="also run a plain device-to-device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU; --gpus must be 1 "
-              "(independent problems shard across GPUs without exchange, see DESIGN.md)",
+        print("bench.py: measures one GPU only; --gpus must be 1 (the path has no multi-GPU "
+              "launch: independent problems would shard across GPUs without exchange)",
               file=sys.stderr)
         sys.exit(2)
 
