@@ -178,6 +178,9 @@ def batched_section(torch, steps, n=512, seed=0, dt=0.02, flag=0, compact=False)
         work = torch.empty(S._round(info["work_bytes_fp64"]), dtype=torch.uint8, device="cuda")
         inst.append((q, T, params, y, work, T.tier0_pure(1.0, 0.0, [0.0] * q.d), info["n_var"]))
     nv = sum(x[6] for x in inst)
+    # tables every stage reads: each instance's tiles read its structure's
+    # metadata (shared images are re-read per instance)
+    tab = sum(x[1].info()["stage_table_bytes"] for x in inst)
     batch = heom.Batch(len(inst))
     obs_bufs = []
     for i, (q, T, params, y, work, t0v, _) in enumerate(inst):
@@ -191,7 +194,8 @@ def batched_section(torch, steps, n=512, seed=0, dt=0.02, flag=0, compact=False)
            "instances": len(inst), "unique_vars_total": nv, "structure_keys": len(structs),
            "largest_instance_vars": max(x[6] for x in inst),
            "median_instance_vars": int(sorted(x[6] for x in inst)[len(inst) // 2]),
-           "steps": steps, "table_build_s": round(build_s, 2), "hermitian_ados": bool(flag)}
+           "steps": steps, "table_build_s": round(build_s, 2), "hermitian_ados": bool(flag),
+           "table_bytes_read_per_stage": tab}
     for prec, name in ((0, "fp64_batched"), (1, "fp32_batched")):
         for q, T, params, y, work, t0v, _ in inst:
             T.init_state(t0v, y, st)
@@ -203,6 +207,11 @@ def batched_section(torch, steps, n=512, seed=0, dt=0.02, flag=0, compact=False)
         e1.record(st)
         torch.cuda.synchronize()
         out[name] = _rate(e0.elapsed_time(e1), len(inst), nv, steps)
+        # algorithmic bytes of one RK4 step (state as stage_bytes_per_var
+        # counts it, plus four stages of table reads) over the step time
+        gbs = (nv * stage_bytes_per_var(prec) + 4 * tab) / (out[name]["ms_per_step"] * 1e-3) / 1e9
+        out[name]["algorithmic_GBps"] = round(gbs, 1)
+        out[name]["hbm_frac"] = round(gbs / HBM_PEAK_GBS, 4)
         out[name]["finite"] = bool(all(torch.isfinite(x[3][:64]).all().item() for x in inst[:64]))
     # every slot recorded its observables after 1 + steps FP64 steps (row 1) and,
     # from the same start, after 1 + steps FP32 steps (row 2)
