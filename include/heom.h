@@ -141,7 +141,7 @@ int heom_tier0_pure(const heom_tables *t, const double a_c[2], const double *a_d
 /* Tier-0 unique variables of any operator A on the single-excitation space
  * that is invariant under relabelings of the pool molecules (Hermitian or
  * not, e.g. the representative operators |e_1><c|, |e_1><e_2| of the
- * linear reconstruction of Sec. VII.A, Table II). A is given by its
+ * linear reconstruction of Sec. VI.C, Table II). A is given by its
  * entries between representative basis states, R[a][b] = <a|A|b>, on the
  * d+3 slots 0 = cavity, 1..d = distinguished molecules e_1..e_d, d+1 = a
  * pool molecule, d+2 = a second pool molecule: R is (d+3)x(d+3) complex,
@@ -164,20 +164,31 @@ int heom_tier0_expand(const heom_tables *t, const double *tier0, double *R);
  * 2*tier0_size doubles) and zeros elsewhere. Requires heom_upload. */
 int heom_init_state(const heom_tables *t, const double *tier0, void *y_dev, void *stream);
 
-/* One matrix-free right-hand side dy = M_u y (Eq. uvar-propagator), complex
- * FP64: the commutator with H_S through grouped multiplicity sums
- * (Eqs. grouped-row-sum, grouped-column-sum, HZ, HX), -Gamma_Lambda damping
+/* One matrix-free right-hand side dy = M_u y (Eq. uvar-propagator): the
+ * commutator with H_S through grouped multiplicity sums (Eqs.
+ * grouped-row-sum, grouped-column-sum, HZ, HX), -Gamma_Lambda damping
  * (Eq. Gamma-Lambda-one and its m-channel form), cavity loss, the terminator
  * if set, and the hierarchy couplings read through the connection records
- * (Eqs. uvar-up, uvar-down). y_dev and dy_dev: n_var complex128, distinct.
- * work_dev: rhs_work_bytes of device scratch (the transposed copy of y when
- * the tables keep transposed copies; may be NULL when rhs_work_bytes is 0).
- * Requires heom_upload. Errors: E_TOO_LARGE if work_bytes is too small. */
+ * (Eqs. uvar-up, uvar-down). y_dev and dy_dev: n_var values each, distinct.
+ *   precision HEOM_FP64: complex128 in and out, FP64 arithmetic.
+ *   precision HEOM_FP32: complex64 in and out (the FP32 bulk of
+ *     heom_propagate); multiplicities, square-root weights, damping and the
+ *     arithmetic are FP64, the result is rounded to complex64 once.
+ *   | HEOM_HERMITIAN: the caller asserts that every ADO of y is Hermitian
+ *     (see heom_propagate). Tables with transposed column targets then read
+ *     the conjugated mirrored entry of y for column moves; compact tables
+ *     (heom_tuning.compact), which need this flag, compute each block's upper
+ *     triangle and T_q and write every entry of dy (the lower triangle as
+ *     the conjugates). Errors: E_INVAL if c_check != conj(c).
+ * work_dev: scratch for the transposed copy of y, needed only by tables with
+ * transposed column targets without HEOM_HERMITIAN (rhs_work_bytes; may be
+ * NULL otherwise). Requires heom_upload. Errors: E_TOO_LARGE if work_bytes
+ * is too small, E_STATE for compact tables without HEOM_HERMITIAN. */
 int heom_rhs(const heom_tables *t, const void *y_dev, void *dy_dev, void *work_dev, size_t work_bytes,
-             void *stream);
+             int precision, void *stream);
 
 /* Propagate y_dev in place by nsteps classical RK4 steps of size dt (the
- * integrator of Sec. VII.C). The linear generator is autonomous, so a step
+ * integrator of Sec. VII.E). The linear generator is autonomous, so a step
  * is evaluated as y + h M (y + h/2 M (y + h/3 M (y + h/4 M y))), the same
  * degree-4 polynomial in hM as the k1..k4 form, with four fused
  * right-hand-side + combination stages.
@@ -241,8 +252,10 @@ int heom_export_coefficients(const heom_tables *t, double *out, size_t cap, size
 typedef struct heom_tuning {
     int32_t tile_vars;       /* variables per workgroup tile: 64, 128, 256 or 512 (0 = keep) */
     int32_t persistent;      /* 1: heom_propagate runs all steps in one cooperative launch with a
-                                grid barrier after each stage; 0: one launch per stage;
-                                2 (default): persistent when the state has at most 256 tiles */
+                                grid barrier after each stage (check heom_work_status afterwards:
+                                a barrier that times out leaves the state mid-step); 0 (default):
+                                one launch per stage; 2: persistent when the state has at most
+                                256 tiles */
     int32_t xcd_map;         /* 1: map workgroups to tiles so each XCD streams a contiguous run */
     int32_t max_workgroups;  /* cap on resident workgroups of the persistent launch (0 = occupancy limit) */
     int32_t spin_limit;      /* polls before a grid barrier gives up (0 = default, about 4 s) */
@@ -278,10 +291,13 @@ typedef struct heom_tuning {
 int heom_set_tuning(heom_tables *t, const heom_tuning *tuning);
 int heom_get_tuning(const heom_tables *t, heom_tuning *tuning);
 
-/* Wait for `stream` and report whether the last heom_propagate that used
- * this work buffer completed: HEOM_OK, or HEOM_E_TIMEOUT if a grid barrier of
- * the persistent kernel gave up (the state is then invalid). Reads 4 bytes of
- * work_dev. */
+/* Wait for `stream` and report how the last heom_propagate that used this
+ * work buffer ended: HEOM_OK; HEOM_E_TIMEOUT if a grid barrier of the
+ * persistent kernel gave up (the state is then invalid); HEOM_E_NONFINITE if
+ * the tier-0 block of the final state or an observable row written by that
+ * call is NaN or infinite (an unstable dt, for instance). heom_propagate
+ * itself returns before the device finishes, so it cannot report these.
+ * Reads 8 bytes of work_dev. */
 int heom_work_status(const heom_tables *t, const void *work_dev, size_t work_bytes, void *stream);
 
 /* Release a handle (NULL is allowed). Device memory is the caller's. */
@@ -311,7 +327,9 @@ int heom_batch_create(int32_t capacity, heom_batch **out);
 
 /* Put a problem into a slot (replacing what was there): its structure `t`
  * (uploaded, kept alive and unmoved by the caller), its parameter block
- * (NULL = the parameters uploaded with t), its state y_dev (t's layout,
+ * (written by heom_upload_params for t and t's current tiles; NULL = the
+ * parameters in t's own image, wherever t is uploaded at the next commit),
+ * its state y_dev (t's layout,
  * complex128, initialized e.g. by heom_init_state), a work buffer of at least
  * work_bytes_fp64 bytes, its time step, and optionally an observable buffer
  * of obs_capacity samples of HEOM_NOBS doubles: sample j holds the
@@ -333,9 +351,12 @@ int heom_batch_device_bytes(const heom_batch *b, size_t *bytes);
 /* Upload the slot records and the tile list (grouped by m) into caller
  * device memory (256-byte aligned, >= heom_batch_device_bytes), and write
  * observable sample 0 of every slot that has not stepped yet, synchronously
- * on `stream`. Required after any set/clear, and after re-tuning a slot's
- * tables. Errors: E_STATE if a slot's tables are not uploaded, E_TOO_LARGE
- * if a slot's work buffer is smaller than its tables' work_bytes now. */
+ * on `stream`. Required after any set/clear, and after re-tuning or
+ * re-uploading a slot's tables. Errors: E_STATE if a slot's tables are not
+ * uploaded, or its parameter block was not written by heom_upload_params for
+ * those tables and their current tiles (re-tuning tiles makes earlier blocks
+ * stale); E_TOO_LARGE if a slot's work buffer is smaller than its tables'
+ * work_bytes now. */
 int heom_batch_commit(heom_batch *b, void *dev, size_t bytes, void *stream);
 
 /* Advance every occupied slot by nsteps RK4 steps of its own dt (the same
@@ -343,8 +364,9 @@ int heom_batch_commit(heom_batch *b, void *dev, size_t bytes, void *stream);
  * tiles of all slots; slots whose tables keep transposed copies get the copy
  * of y made at the start of each call). Each problem's trajectory is bitwise the same as with
  * heom_propagate alone (no slot reads another slot's memory). precision as
- * in heom_propagate, HEOM_HERMITIAN included (not checked against the slots'
- * parameter blocks here: the caller asserts it for every slot). Errors: E_STATE if not committed since the last change. */
+ * in heom_propagate, HEOM_HERMITIAN included (E_INVAL unless every slot's
+ * parameters have c_check = conj(c)). Errors: E_STATE if not committed since
+ * the last change. Non-finite states are reported by heom_batch_status. */
 int heom_batch_propagate(heom_batch *b, int64_t nsteps, int precision, void *stream);
 
 /* Replay whole groups of `steps` RK4 steps from a HIP graph captured on the
@@ -370,6 +392,14 @@ int heom_batch_set_graph(heom_batch *b, int32_t steps);
  * Results are bitwise the same either way. Takes effect at the next
  * heom_batch_commit (required). */
 int heom_batch_set_merge(heom_batch *b, int32_t max_tiles);
+
+/* Wait for `stream` and report whether any occupied slot's tier-0 block
+ * became NaN or infinite during a heom_batch_propagate since the last
+ * heom_batch_commit (which clears the flags): HEOM_E_NONFINITE if so, else
+ * HEOM_OK. slot_flags (host, may be NULL when cap is 0) receives 1 or 0 for
+ * the first `cap` slots. Errors: E_STATE if not committed since the last
+ * change. */
+int heom_batch_status(const heom_batch *b, int32_t *slot_flags, int32_t cap, void *stream);
 
 /* Steps a slot has taken since it was set. */
 int heom_batch_slot_steps(const heom_batch *b, int32_t slot, int64_t *steps);

@@ -1,6 +1,6 @@
 """Classical fourth-order Runge-Kutta (oracle; test infrastructure only).
 
-The paper propagates with a conventional RK4 (Sec. VII.A, remark on work
+The paper propagates with a conventional RK4 (Sec. VII.E, remark on work
 arrays). For the autonomous linear system dy/dt = A y one step is
     k1 = A y, k2 = A(y + h/2 k1), k3 = A(y + h/2 k2), k4 = A(y + h k3),
     y <- y + h/6 (k1 + 2 k2 + 2 k3 + k4).

@@ -13,8 +13,10 @@
 
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <new>
 #include <string>
+#include <unordered_map>
 
 #include "heom_internal.h"
 
@@ -27,7 +29,8 @@ struct heom_tables {
 struct BatchSlotHost {
     bool used = false;
     const heom_tables *tables = nullptr;
-    const void *params = nullptr;
+    const void *params = nullptr;   // caller's parameter block, or null: the one in the tables' image
+    bool adjoint = false;           // c_check = conj(c) for this slot's parameters (resolved at commit)
     void *y = nullptr, *work = nullptr;
     size_t work_bytes = 0;
     double dt = 0.0;
@@ -95,6 +98,19 @@ struct heom_batch {
 namespace {
 
 thread_local std::string g_err;
+
+// Parameter blocks written by heom_upload_params, by device address: the
+// tables handle and image layout they were written for, and whether their
+// bath maps Hermitian ADOs to Hermitian ADOs. A batch commit checks a slot's
+// block against its tables here, so a block left over from before a
+// re-tuning (other LDS layout, section offsets or tile kind) is refused
+// instead of read.
+struct ParamsStamp {
+    uint64_t tables_id, layout_gen;
+    bool adjoint;
+};
+std::mutex g_params_mu;
+std::unordered_map<uintptr_t, ParamsStamp> g_params;
 
 int fail(int code, const std::string &msg) {
     g_err = msg;
@@ -923,15 +939,38 @@ __global__ void observables_kernel(Dev D, const double2 *y, double *obs) {
     if (threadIdx.x == 0) tier0_observables(*D.ip, D.hdr[0], D.cat, v, obs);
 }
 
+// Non-finite check at the end of a propagation: the tier-0 block of y (the
+// observables' input) and the observable rows the call wrote. Any thread that
+// sees a NaN or an infinity makes thread 0 set *flag.
+__global__ void finite_check_kernel(const double *y0, uint32_t n_y0, const double *obs, uint32_t n_obs,
+                                    uint32_t *flag) {
+    int bad = 0;
+    for (uint32_t i = threadIdx.x; i < n_y0; i += blockDim.x) bad |= !__builtin_isfinite(y0[i]);
+    for (uint32_t i = threadIdx.x; i < n_obs; i += blockDim.x) bad |= !__builtin_isfinite(obs[i]);
+    if (__syncthreads_or(bad) && threadIdx.x == 0) *flag = 1u;
+}
+
+// The same for every occupied slot of a batch (one workgroup per slot): the
+// tier-0 block of the slot's state; flags[slot] is set if it is not finite.
+__global__ void batch_finite_kernel(const SlotRec *slots, uint32_t *flags) {
+    const SlotRec R = slots[blockIdx.x];
+    if (R.y == nullptr) return;            // an empty slot: the whole workgroup leaves
+    const uint32_t n = 2u * as_global(R.hdr)[0].size;
+    const double *y0 = reinterpret_cast<const double *>(as_global(R.y));
+    int bad = 0;
+    for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) bad |= !__builtin_isfinite(y0[i]);
+    if (__syncthreads_or(bad) && threadIdx.x == 0) flags[blockIdx.x] = 1u;
+}
+
 __global__ void zero_kernel(double2 *y, uint32_t n) {
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
         y[i] = make_double2(0.0, 0.0);
 }
 
 // yT = y with every block's category matrix transposed (T_q in place); one
-// workgroup per tile, one thread per variable.
-__global__ void transpose_kernel(const TileRec *tiles, const VarRec *vrec, const PatHdr *hdr, const double2 *y,
-                                 double2 *yT) {
+// workgroup per tile, one thread per variable (complex FP64 or FP32 values).
+template <class V>
+__global__ void transpose_kernel(const TileRec *tiles, const VarRec *vrec, const PatHdr *hdr, const V *y, V *yT) {
     const TileRec TR = tiles[blockIdx.x];
     const uint32_t t = threadIdx.x;
     if (t >= TR.nv) return;
@@ -956,20 +995,17 @@ void launch_m(const HostTables &t, hipStream_t s, StageArgs a) {
     // kernel that has no up-move slots, fewer registers and more waves.
     const uint32_t split = (T >= TOP_SPLIT_TILES && t.top_tile > 0 && t.top_tile < T) ? t.top_tile : T;
     a.tile0 = 0;
-    // compact tiles have kernels of their own (heom_rhs, the stage without a
-    // base or extra term and with FP64 output, refuses them before this)
-    if constexpr (!(BASE == BASE_NONE && !EXTRA && OUT64)) {
-        if (t.compact) {
-            hipLaunchKernelGGL((stage_kernel<M, HAS64, HAS32, BASE, EXTRA, OUT64, false, 1>), dim3(split),
-                               dim3(t.tile_vars), split < T ? t.lds_low : t.lds_bytes, s, dev_view(t), a,
-                               t.tune.xcd_map);
-            if (split < T) {
-                a.tile0 = split;
-                hipLaunchKernelGGL((stage_kernel<M, HAS64, HAS32, BASE, EXTRA, OUT64, true, 1>), dim3(T - split),
-                                   dim3(t.tile_vars), t.lds_top, s, dev_view(t), a, t.tune.xcd_map);
-            }
-            return;
+    // compact tiles (Hermitian ADOs) have kernels of their own
+    if (t.compact) {
+        hipLaunchKernelGGL((stage_kernel<M, HAS64, HAS32, BASE, EXTRA, OUT64, false, 1>), dim3(split),
+                           dim3(t.tile_vars), split < T ? t.lds_low : t.lds_bytes, s, dev_view(t), a,
+                           t.tune.xcd_map);
+        if (split < T) {
+            a.tile0 = split;
+            hipLaunchKernelGGL((stage_kernel<M, HAS64, HAS32, BASE, EXTRA, OUT64, true, 1>), dim3(T - split),
+                               dim3(t.tile_vars), t.lds_top, s, dev_view(t), a, t.tune.xcd_map);
         }
+        return;
     }
     hipLaunchKernelGGL((stage_kernel<M, HAS64, HAS32, BASE, EXTRA, OUT64, false, 0>), dim3(split),
                        dim3(t.tile_vars), split < T ? t.lds_low : t.lds_bytes, s, dev_view(t), a, t.tune.xcd_map);
@@ -999,8 +1035,8 @@ __global__ void zero_u32_kernel(uint32_t *p, uint32_t n) {
 }
 
 // Control area of the work buffer, after the state-sized vectors:
-//   byte 4: barrier timeout word; bytes 256..: one 64-byte flag slot per
-//   persistent workgroup.
+//   byte 4: barrier timeout word; byte 8: non-finite flag of the last
+//   propagation; bytes 256..: one 64-byte flag slot per persistent workgroup.
 constexpr uint32_t MAX_PERSIST_WG = 2048;
 constexpr size_t CTRL_BYTES = 256 + 64 * (size_t)MAX_PERSIST_WG;
 
@@ -1040,9 +1076,10 @@ WorkView work_view(const HostTables &t, void *work) {
     return w;
 }
 
-int launch_transpose(const HostTables &t, hipStream_t s, const double2 *y, double2 *yT) {
+template <class V>
+int launch_transpose(const HostTables &t, hipStream_t s, const V *y, V *yT) {
     const Dev D = dev_view(t);
-    hipLaunchKernelGGL(transpose_kernel, dim3((uint32_t)t.tiles.size()), dim3(t.tile_vars), 0, s, D.tiles, D.vrec,
+    hipLaunchKernelGGL(transpose_kernel<V>, dim3((uint32_t)t.tiles.size()), dim3(t.tile_vars), 0, s, D.tiles, D.vrec,
                        D.hdr, y, yT);
     HIP_TRY(hipGetLastError());
     return HEOM_OK;
@@ -1098,6 +1135,13 @@ size_t rhs_work_bytes_for(const HostTables &t) { return has_copies(t) ? (size_t)
 bool adjoint_preserving(const HostTables &t) {
     for (int k = 0; k < t.m; ++k)
         if (t.cc[2 * k] != t.c[2 * k] || t.cc[2 * k + 1] != -t.c[2 * k + 1]) return false;
+    return true;
+}
+
+bool adjoint_preserving(const heom_problem &p) {
+    if (!p.c_check) return true;
+    for (int k = 0; k < p.m; ++k)
+        if (p.c_check[2 * k] != p.c[2 * k] || p.c_check[2 * k + 1] != -p.c[2 * k + 1]) return false;
     return true;
 }
 
@@ -1221,6 +1265,67 @@ int batch_capture(heom_batch *b, hipStream_t s, int precision) {
         return fail(HEOM_E_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(ei));
     }
     b->gprec = precision;
+    return HEOM_OK;
+}
+
+// heom_propagate without the persistent kernel: one launch per RK4 stage.
+int propagate_stages(const HostTables &t, hipStream_t s, double2 *y, const WorkView &wv, const PersistArgs &pa,
+                     int precision, bool hermitian, double dt, int64_t nsteps, int64_t obs_every, double *obs_dev) {
+    // one launch per stage; with transposed copies, y's copy is made once
+    // here and each stage then writes the copy of its own output. Hermitian
+    // ADOs need no copies: column gathers read the mirrored entry.
+    const double h1 = dt / 4.0, h2 = dt / 3.0, h3 = dt / 2.0, h4 = dt;
+    int rc;
+    const bool mirror = hermitian && t.trcol;
+    WorkView cv = wv;                       // the copies, or none
+    if (mirror) cv.yT = cv.w0T = cv.w1T = nullptr, cv.u1T = cv.u2T = cv.u3T = nullptr;
+    const uint32_t pol = mirror ? 8u : 0u;
+    if (t.trcol && !mirror && (rc = launch_transpose(t, s, y, wv.yT))) return rc;
+    if (precision == HEOM_FP64) {
+        double2 *wa = pa.w0, *wbv = pa.w1, *waT = cv.w0T, *wbT = cv.w1T;
+        for (int64_t st = 1; st <= nsteps; ++st) {
+            double *ob = (obs_every > 0 && st % obs_every == 0) ? obs_dev + (st / obs_every) * HEOM_NOBS : nullptr;
+            StageArgs a{};
+            a.policy = pol;
+            a.in64 = y; a.inT64 = cv.yT; a.out64 = wa; a.outT64 = waT; a.alpha = h1;
+            if ((rc = launch_stage<true, false, BASE_IN, false, true>(t, s, a))) return rc;
+            a = StageArgs{}; a.policy = pol;
+            a.in64 = wa; a.inT64 = waT; a.ybase = y; a.out64 = wbv; a.outT64 = wbT; a.alpha = h2;
+            if ((rc = launch_stage<true, false, BASE_Y, false, true>(t, s, a))) return rc;
+            a = StageArgs{}; a.policy = pol;
+            a.in64 = wbv; a.inT64 = wbT; a.ybase = y; a.out64 = wa; a.outT64 = waT; a.alpha = h3;
+            if ((rc = launch_stage<true, false, BASE_Y, false, true>(t, s, a))) return rc;
+            a = StageArgs{}; a.policy = pol;
+            a.in64 = wa; a.inT64 = waT; a.ybase = y; a.out64 = y; a.outT64 = cv.yT; a.alpha = h4;
+            a.obs = ob;
+            if ((rc = launch_stage<true, false, BASE_Y, false, true>(t, s, a))) return rc;
+        }
+    } else {
+        // u1 = h/4 M y, u2 = h/3 M (y + u1), u3 = h/2 M (y + u2) and
+        // y += h M (y + u3), each from the FP32 increment it gathers plus
+        // M y = (4/h) u1; the state is updated in place by its owner.
+        float2 *u1 = pa.u1, *u2 = pa.u2, *u3 = pa.u3;
+        const double inv_h1 = 1.0 / h1;
+        for (int64_t st = 1; st <= nsteps; ++st) {
+            double *ob = (obs_every > 0 && st % obs_every == 0) ? obs_dev + (st / obs_every) * HEOM_NOBS : nullptr;
+            StageArgs a{};
+            a.policy = pol;
+            a.in64 = y; a.inT64 = cv.yT; a.out32 = u1; a.outT32 = cv.u1T; a.alpha = h1;
+            if ((rc = launch_stage<true, false, BASE_NONE, false, false>(t, s, a))) return rc;
+            a = StageArgs{}; a.policy = pol;
+            a.in32 = u1; a.inT32 = cv.u1T; a.extra = u1; a.extra_scale = inv_h1; a.out32 = u2;
+            a.outT32 = cv.u2T; a.alpha = h2;
+            if ((rc = launch_stage<false, true, BASE_NONE, true, false>(t, s, a))) return rc;
+            a = StageArgs{}; a.policy = pol;
+            a.in32 = u2; a.inT32 = cv.u2T; a.extra = u1; a.extra_scale = inv_h1; a.out32 = u3;
+            a.outT32 = cv.u3T; a.alpha = h3;
+            if ((rc = launch_stage<false, true, BASE_NONE, true, false>(t, s, a))) return rc;
+            a = StageArgs{}; a.policy = pol;
+            a.in32 = u3; a.inT32 = cv.u3T; a.extra = u1; a.extra_scale = inv_h1; a.ybase = y;
+            a.out64 = y; a.outT64 = cv.yT; a.alpha = h4; a.obs = ob;
+            if ((rc = launch_stage<false, true, BASE_Y, true, true>(t, s, a))) return rc;
+        }
+    }
     return HEOM_OK;
 }
 
@@ -1408,28 +1513,49 @@ int heom_init_state(const heom_tables *h, const double *tier0, void *y_dev, void
 }
 
 int heom_rhs(const heom_tables *h, const void *y_dev, void *dy_dev, void *work_dev, size_t work_bytes,
-             void *stream) {
+             int precision, void *stream) {
     if (int rc = check_ready(h)) return rc;
     if (int rc = check_dev(y_dev, "y_dev")) return rc;
     if (int rc = check_dev(dy_dev, "dy_dev")) return rc;
     if (y_dev == dy_dev) return fail(HEOM_E_INVAL, "y_dev and dy_dev must differ");
+    const bool hermitian = (precision & HEOM_HERMITIAN) != 0;
+    precision &= ~HEOM_HERMITIAN;
+    if (precision != HEOM_FP64 && precision != HEOM_FP32) return fail(HEOM_E_INVAL, "unknown precision");
     const HostTables &t = h->t;
-    if (t.compact) return fail(HEOM_E_STATE, "compact tiles serve heom_propagate with HEOM_HERMITIAN only");
-    const size_t need = rhs_work_bytes_for(t);
+    if (hermitian && !adjoint_preserving(t))
+        return fail(HEOM_E_INVAL, "HEOM_HERMITIAN needs c_check = conj(c) for every channel");
+    if (t.compact && !hermitian) return fail(HEOM_E_STATE, "compact tiles need HEOM_HERMITIAN");
+    // column moves of transposed tables read the mirrored entry (Hermitian
+    // ADOs) or a transposed copy of y made here
+    const bool mirror = hermitian && t.trcol;
+    const bool copy = t.trcol && !mirror;
+    const size_t need = copy ? rhs_work_bytes_for(t) : 0;
     if (need > 0 && !work_dev) return fail(HEOM_E_INVAL, "work_dev is NULL");
     if (work_bytes < need) return fail(HEOM_E_TOO_LARGE, "work buffer smaller than rhs_work_bytes");
+    if (copy && (work_dev == y_dev || work_dev == dy_dev)) return fail(HEOM_E_INVAL, "work_dev overlaps y_dev or dy_dev");
     hipStream_t s = static_cast<hipStream_t>(stream);
     StageArgs a{};
-    a.in64 = static_cast<const double2 *>(y_dev);
-    a.out64 = static_cast<double2 *>(dy_dev);
     a.alpha = 1.0;
-    if (t.trcol) {
-        double2 *yT = static_cast<double2 *>(work_dev);
-        if (work_dev == y_dev || work_dev == dy_dev) return fail(HEOM_E_INVAL, "work_dev overlaps y_dev or dy_dev");
-        if (int rc = launch_transpose(t, s, a.in64, yT)) return rc;
-        a.inT64 = yT;
+    a.policy = mirror ? 8u : 0u;
+    if (precision == HEOM_FP64) {
+        a.in64 = static_cast<const double2 *>(y_dev);
+        a.out64 = static_cast<double2 *>(dy_dev);
+        if (copy) {
+            double2 *yT = static_cast<double2 *>(work_dev);
+            if (int rc = launch_transpose(t, s, a.in64, yT)) return rc;
+            a.inT64 = yT;
+        }
+        return launch_stage<true, false, BASE_NONE, false, true>(t, s, a);
     }
-    return launch_stage<true, false, BASE_NONE, false, true>(t, s, a);
+    // FP32 bulk: complex64 values in and out, FP64 weights and arithmetic
+    a.in32 = static_cast<const float2 *>(y_dev);
+    a.out32 = static_cast<float2 *>(dy_dev);
+    if (copy) {
+        float2 *yT = static_cast<float2 *>(work_dev);
+        if (int rc = launch_transpose(t, s, a.in32, yT)) return rc;
+        a.inT32 = yT;
+    }
+    return launch_stage<false, true, BASE_NONE, false, false>(t, s, a);
 }
 
 int heom_observables(const heom_tables *h, const void *y_dev, double *obs_dev, void *stream) {
@@ -1488,66 +1614,18 @@ int heom_propagate(const heom_tables *h, void *y_dev, void *work_dev, size_t wor
     hipLaunchKernelGGL(zero_u32_kernel, dim3(64), dim3(256), 0, s, pa.timeout - 1, (uint32_t)(CTRL_BYTES / 4));
     HIP_TRY(hipGetLastError());
     const bool persist = t.tune.persistent == 1 || (t.tune.persistent == 2 && t.tiles.size() <= 256);
-    if (persist) {
-        bool used = false;
+    bool used = false;
+    if (persist)
         if (int rc = launch_persistent(t, s, pa, precision, &used)) return rc;
-        if (used) return HEOM_OK;
-    }
-    // one launch per stage; with transposed copies, y's copy is made once
-    // here and each stage then writes the copy of its own output. Hermitian
-    // ADOs need no copies: column gathers read the mirrored entry.
-    const double h1 = dt / 4.0, h2 = dt / 3.0, h3 = dt / 2.0, h4 = dt;
-    int rc;
-    const bool mirror = hermitian && t.trcol;
-    WorkView cv = wv;                       // the copies, or none
-    if (mirror) cv.yT = cv.w0T = cv.w1T = nullptr, cv.u1T = cv.u2T = cv.u3T = nullptr;
-    const uint32_t pol = mirror ? 8u : 0u;
-    if (t.trcol && !mirror && (rc = launch_transpose(t, s, y, wv.yT))) return rc;
-    if (precision == HEOM_FP64) {
-        double2 *wa = pa.w0, *wbv = pa.w1, *waT = cv.w0T, *wbT = cv.w1T;
-        for (int64_t st = 1; st <= nsteps; ++st) {
-            double *ob = (obs_every > 0 && st % obs_every == 0) ? obs_dev + (st / obs_every) * HEOM_NOBS : nullptr;
-            StageArgs a{};
-            a.policy = pol;
-            a.in64 = y; a.inT64 = cv.yT; a.out64 = wa; a.outT64 = waT; a.alpha = h1;
-            if ((rc = launch_stage<true, false, BASE_IN, false, true>(t, s, a))) return rc;
-            a = StageArgs{}; a.policy = pol;
-            a.in64 = wa; a.inT64 = waT; a.ybase = y; a.out64 = wbv; a.outT64 = wbT; a.alpha = h2;
-            if ((rc = launch_stage<true, false, BASE_Y, false, true>(t, s, a))) return rc;
-            a = StageArgs{}; a.policy = pol;
-            a.in64 = wbv; a.inT64 = wbT; a.ybase = y; a.out64 = wa; a.outT64 = waT; a.alpha = h3;
-            if ((rc = launch_stage<true, false, BASE_Y, false, true>(t, s, a))) return rc;
-            a = StageArgs{}; a.policy = pol;
-            a.in64 = wa; a.inT64 = waT; a.ybase = y; a.out64 = y; a.outT64 = cv.yT; a.alpha = h4;
-            a.obs = ob;
-            if ((rc = launch_stage<true, false, BASE_Y, false, true>(t, s, a))) return rc;
-        }
-    } else {
-        // u1 = h/4 M y, u2 = h/3 M (y + u1), u3 = h/2 M (y + u2) and
-        // y += h M (y + u3), each from the FP32 increment it gathers plus
-        // M y = (4/h) u1; the state is updated in place by its owner.
-        float2 *u1 = pa.u1, *u2 = pa.u2, *u3 = pa.u3;
-        const double inv_h1 = 1.0 / h1;
-        for (int64_t st = 1; st <= nsteps; ++st) {
-            double *ob = (obs_every > 0 && st % obs_every == 0) ? obs_dev + (st / obs_every) * HEOM_NOBS : nullptr;
-            StageArgs a{};
-            a.policy = pol;
-            a.in64 = y; a.inT64 = cv.yT; a.out32 = u1; a.outT32 = cv.u1T; a.alpha = h1;
-            if ((rc = launch_stage<true, false, BASE_NONE, false, false>(t, s, a))) return rc;
-            a = StageArgs{}; a.policy = pol;
-            a.in32 = u1; a.inT32 = cv.u1T; a.extra = u1; a.extra_scale = inv_h1; a.out32 = u2;
-            a.outT32 = cv.u2T; a.alpha = h2;
-            if ((rc = launch_stage<false, true, BASE_NONE, true, false>(t, s, a))) return rc;
-            a = StageArgs{}; a.policy = pol;
-            a.in32 = u2; a.inT32 = cv.u2T; a.extra = u1; a.extra_scale = inv_h1; a.out32 = u3;
-            a.outT32 = cv.u3T; a.alpha = h3;
-            if ((rc = launch_stage<false, true, BASE_NONE, true, false>(t, s, a))) return rc;
-            a = StageArgs{}; a.policy = pol;
-            a.in32 = u3; a.inT32 = cv.u3T; a.extra = u1; a.extra_scale = inv_h1; a.ybase = y;
-            a.out64 = y; a.outT64 = cv.yT; a.alpha = h4; a.obs = ob;
-            if ((rc = launch_stage<false, true, BASE_Y, true, true>(t, s, a))) return rc;
-        }
-    }
+    if (!used)
+        if (int rc = propagate_stages(t, s, y, wv, pa, precision, hermitian, dt, nsteps, obs_every, obs_dev))
+            return rc;
+    // flag a non-finite tier-0 block or observable (heom_work_status reports it)
+    const uint32_t n_obs = obs_every > 0 ? (uint32_t)((nsteps / obs_every + 1) * HEOM_NOBS) : 0u;
+    hipLaunchKernelGGL(finite_check_kernel, dim3(1), dim3(256), 0, s, reinterpret_cast<const double *>(y),
+                       (uint32_t)(2 * tier0_size(t)), obs_every > 0 ? obs_dev : nullptr, n_obs,
+                       reinterpret_cast<uint32_t *>(wv.ctrl + 8));
+    HIP_TRY(hipGetLastError());
     return HEOM_OK;
 }
 
@@ -1586,11 +1664,13 @@ int heom_work_status(const heom_tables *h, const void *work_dev, size_t work_byt
     if (!h || !work_dev) return fail(HEOM_E_INVAL, "NULL argument");
     if (work_bytes < work_bytes_for(h->t)) return fail(HEOM_E_TOO_LARGE, "work buffer smaller than work_bytes");
     hipStream_t s = static_cast<hipStream_t>(stream);
-    uint32_t flag = 0;
+    uint32_t flag[2] = {0u, 0u};            // timeout word, non-finite flag
     const unsigned char *p = static_cast<const unsigned char *>(work_dev) + vec_bytes(h->t) + 4;
-    HIP_TRY(hipMemcpyAsync(&flag, p, 4, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(flag, p, 8, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
-    return flag ? fail(HEOM_E_TIMEOUT, "a grid barrier of the persistent kernel timed out") : HEOM_OK;
+    if (flag[0]) return fail(HEOM_E_TIMEOUT, "a grid barrier of the persistent kernel timed out");
+    if (flag[1]) return fail(HEOM_E_NONFINITE, "the propagated tier-0 block or an observable is not finite");
+    return HEOM_OK;
 }
 
 int heom_get_tuning(const heom_tables *h, heom_tuning *tu) {
@@ -1687,6 +1767,8 @@ int heom_upload_params(const heom_tables *h, const heom_problem *prob, void *dev
     hipStream_t s = static_cast<hipStream_t>(stream);
     HIP_TRY(hipMemcpyAsync(dev, blk.data(), blk.size(), hipMemcpyHostToDevice, s));
     HIP_TRY(hipStreamSynchronize(s));
+    std::lock_guard<std::mutex> lk(g_params_mu);
+    g_params[reinterpret_cast<uintptr_t>(dev)] = ParamsStamp{h->t.id, h->t.layout_gen, adjoint_preserving(*prob)};
     return HEOM_OK;
 }
 
@@ -1714,7 +1796,7 @@ int heom_batch_set_slot(heom_batch *b, int32_t slot, const heom_tables *t, const
     BatchSlotHost &S = b->slots[(size_t)slot];
     S.used = true;
     S.tables = t;
-    S.params = params_dev ? params_dev : t->t.dev;
+    S.params = params_dev;
     S.y = y_dev;
     S.work = work_dev;
     S.work_bytes = work_bytes;
@@ -1739,9 +1821,10 @@ int heom_batch_device_bytes(const heom_batch *b, size_t *bytes) {
     size_t nt = 0;
     for (const auto &S : b->slots)
         if (S.used) nt += S.tables->t.tiles.size();
-    // slot records, tile list, then the 8-byte step counter on its own 256 bytes
+    // slot records, tile list, then the 8-byte step counter and the slots'
+    // non-finite flags (4 bytes each)
     *bytes = ((sizeof(SlotRec) * b->slots.size() + 255) & ~(size_t)255) + ((sizeof(BatchTile) * nt + 255) & ~(size_t)255) +
-             256;
+             ((8 + 4 * b->slots.size() + 255) & ~(size_t)255);
     return HEOM_OK;
 }
 
@@ -1753,12 +1836,28 @@ int heom_batch_commit(heom_batch *b, void *dev, size_t bytes, void *stream) {
     if (bytes < need) return fail(HEOM_E_TOO_LARGE, "batch buffer smaller than heom_batch_device_bytes");
     const size_t ns = b->slots.size();
     const size_t tile_off = (sizeof(SlotRec) * ns + 255) & ~(size_t)255;
-    // the tables of a slot may have been re-tuned since heom_batch_set_slot
-    for (const auto &S : b->slots) {
+    // the tables of a slot may have been re-tuned or re-uploaded since
+    // heom_batch_set_slot: every pointer into their image is resolved here,
+    // and a caller's parameter block must have been written for the tables'
+    // current layout
+    for (auto &S : b->slots) {
         if (!S.used) continue;
         if (int rc = check_ready(S.tables)) return rc;
-        if (S.work_bytes < work_bytes_for(S.tables->t))
+        const HostTables &t = S.tables->t;
+        if (S.work_bytes < work_bytes_for(t))
             return fail(HEOM_E_TOO_LARGE, "a slot's work buffer is smaller than its tables' work_bytes");
+        if (!S.params) {
+            S.adjoint = adjoint_preserving(t);
+            continue;
+        }
+        std::lock_guard<std::mutex> lk(g_params_mu);
+        const auto it = g_params.find(reinterpret_cast<uintptr_t>(S.params));
+        if (it == g_params.end() || it->second.tables_id != t.id)
+            return fail(HEOM_E_STATE, "a slot's parameter block was not written by heom_upload_params for its tables");
+        if (it->second.layout_gen != t.layout_gen)
+            return fail(HEOM_E_STATE, "a slot's parameter block predates a re-tuning of its tables "
+                                      "(write it again with heom_upload_params)");
+        S.adjoint = it->second.adjoint;
     }
     std::vector<unsigned char> img(need, 0);
     SlotRec *recs = reinterpret_cast<SlotRec *>(img.data());
@@ -1770,7 +1869,7 @@ int heom_batch_commit(heom_batch *b, void *dev, size_t bytes, void *stream) {
         const HostTables &t = S.tables->t;
         SlotRec &R = recs[i];
         R.img = static_cast<const unsigned char *>(t.dev);
-        R.params = static_cast<const unsigned char *>(S.params);
+        R.params = static_cast<const unsigned char *>(S.params ? S.params : t.dev);
         const Dev D = dev_view(t);
         R.hdr = D.hdr;
         R.cat = D.cat;
@@ -1889,7 +1988,7 @@ int heom_batch_commit(heom_batch *b, void *dev, size_t bytes, void *stream) {
     for (const auto &S : b->slots) {
         if (!S.used || S.steps != 0 || !S.obs || S.obs_every <= 0 || S.obs_cap <= 0) continue;
         Dev D = dev_view(S.tables->t);
-        D.ip = static_cast<const InstParams *>(S.params);
+        D.ip = static_cast<const InstParams *>(S.params ? S.params : S.tables->t.dev);
         hipLaunchKernelGGL(observables_kernel, dim3(1), dim3(64), 0, s, D, static_cast<const double2 *>(S.y), S.obs);
         HIP_TRY(hipGetLastError());
     }
@@ -1909,9 +2008,13 @@ int heom_batch_propagate(heom_batch *b, int64_t nsteps, int precision, void *str
     if (base_prec != HEOM_FP64 && base_prec != HEOM_FP32) return fail(HEOM_E_INVAL, "unknown precision");
     hipStream_t s = static_cast<hipStream_t>(stream);
     if (nsteps == 0) return HEOM_OK;
-    for (const auto &S : b->slots)
-        if (S.used && S.tables->t.compact && !(precision & HEOM_HERMITIAN))
+    for (const auto &S : b->slots) {
+        if (!S.used) continue;
+        if (S.tables->t.compact && !(precision & HEOM_HERMITIAN))
             return fail(HEOM_E_STATE, "a slot has compact tiles, which need HEOM_HERMITIAN");
+        if ((precision & HEOM_HERMITIAN) && !S.adjoint)
+            return fail(HEOM_E_INVAL, "HEOM_HERMITIAN needs c_check = conj(c) in every slot's parameters");
+    }
     // slots with transposed copies: the copy of y, made once per call
     // (Hermitian ADOs use no copies)
     for (size_t i = 0; i < b->slots.size(); ++i) {
@@ -1930,10 +2033,32 @@ int heom_batch_propagate(heom_batch *b, int64_t nsteps, int precision, void *str
     }
     for (; done < nsteps; ++done)
         if (int rc = batch_step(b, s, precision)) return rc;
+    // flag slots whose tier-0 block is no longer finite (heom_batch_status)
+    unsigned char *base = static_cast<unsigned char *>(b->dev);
+    hipLaunchKernelGGL(batch_finite_kernel, dim3((uint32_t)b->slots.size()), dim3(64), 0, s,
+                       static_cast<const SlotRec *>(b->dev), reinterpret_cast<uint32_t *>(base + b->ctr_off + 8));
+    HIP_TRY(hipGetLastError());
     b->steps_since_commit += nsteps;
     for (auto &S : b->slots)
         if (S.used) S.steps += nsteps;
     return HEOM_OK;
+}
+
+int heom_batch_status(const heom_batch *b, int32_t *slot_flags, int32_t cap, void *stream) {
+    if (!b || cap < 0 || (cap > 0 && !slot_flags)) return fail(HEOM_E_INVAL, "bad argument");
+    if (!b->committed) return fail(HEOM_E_STATE, "batch changed since the last heom_batch_commit");
+    const size_t ns = b->slots.size();
+    std::vector<uint32_t> fl(ns, 0u);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    HIP_TRY(hipMemcpyAsync(fl.data(), static_cast<const unsigned char *>(b->dev) + b->ctr_off + 8, 4 * ns,
+                           hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    bool any = false;
+    for (size_t i = 0; i < ns; ++i) {
+        if (i < (size_t)cap) slot_flags[i] = fl[i] ? 1 : 0;
+        any |= fl[i] != 0u;
+    }
+    return any ? fail(HEOM_E_NONFINITE, "a slot's tier-0 block is not finite") : HEOM_OK;
 }
 
 int heom_batch_slot_steps(const heom_batch *b, int32_t slot, int64_t *steps) {

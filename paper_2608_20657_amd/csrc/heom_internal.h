@@ -175,6 +175,8 @@ struct HostTables {
     void *dev = nullptr;                // uploaded image
     size_t dev_bytes = 0;
     bool uploaded = false;
+    uint64_t id = 0;                    // unique per built handle (never reused in a process)
+    uint64_t layout_gen = 0;            // advanced whenever the tiles, and so the image layout, change
 };
 
 // States of at least this many variables keep transposed copies by default.

@@ -9,6 +9,7 @@
 // is the correctly ordered, unfused expression written here.
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdio>
 #include <functional>
@@ -119,6 +120,8 @@ static void copy_numeric(HostTables *t, const heom_problem *p) {
 int build(const heom_problem *p, HostTables *t, std::string *err) {
     int rc = check_params(p, err);
     if (rc) return rc;
+    static std::atomic<uint64_t> next_id{1};
+    t->id = next_id.fetch_add(1);
     const int m = p->m, L = p->L, d = p->d;
     const int64_t N = p->N;
     t->m = m; t->L = L; t->d = d;
@@ -422,8 +425,8 @@ void expand_gathers(const HostTables &t, uint32_t p, std::vector<uint32_t> *out)
     const PatHdr &H = t.hdr[p];
     const int G = H.G, G1 = G + 1, M = t.m;
     const bool chi = H.tier < t.L;
-    const CatRec *cats = &t.cat[H.cat_base];
-    const Conn *cons = &t.conn[H.conn_base];
+    const CatRec *cats = t.cat.data() + H.cat_base;
+    const Conn *cons = t.conn.data() + H.conn_base;   // may be one past the end: a pattern with no moves
     auto rup = [&](const CatRec &c, int k) { return cons[c.conn_off + k]; };
     auto rdn = [&](const CatRec &c, int k) {
         uint32_t r = c.conn_off + (chi ? M : 0);
@@ -480,7 +483,7 @@ static int var_records(const HostTables &t, const TileRec &r, std::vector<VarRec
         const PatHdr &H = t.hdr[r.p0 + pi];
         const int G = H.G, G1 = G + 1;
         const bool chi = H.tier < t.L;
-        const CatRec *cats = &t.cat[H.cat_base];
+        const CatRec *cats = t.cat.data() + H.cat_base;
         for (uint32_t loc = 0; loc < H.size; ++loc) {
             int A, B;
             bool isT = false;
@@ -518,6 +521,7 @@ int make_tiles(HostTables *t, int tile_vars, std::string *err) {
         return HEOM_E_INVAL;
     }
     t->tile_vars = tile_vars;
+    t->layout_gen += 1;
     t->compact = t->tune.compact != 0;
     t->trcol = t->compact || (t->tune.transposed < 0 ? t->n_var >= TRANSPOSED_MIN_VARS : t->tune.transposed != 0);
     t->tiles.clear();
@@ -674,6 +678,13 @@ size_t image_bytes(const HostTables &t) {
     return align256(ip.off_vloc + t.vloc.size() * sizeof(uint16_t));
 }
 
+// Copy a section into the image (an empty section copies nothing: memcpy
+// from the null data() of an empty vector would be undefined).
+template <class V>
+static void put_section(std::vector<unsigned char> *img, uint64_t off, const std::vector<V> &v) {
+    if (!v.empty()) std::memcpy(img->data() + off, v.data(), v.size() * sizeof(V));
+}
+
 int pack_params(const HostTables &t, const heom_problem *p, std::vector<unsigned char> *out, std::string *err) {
     int rc = check_params(p, err);
     if (rc) return rc;
@@ -692,7 +703,7 @@ int pack_params(const HostTables &t, const heom_problem *p, std::vector<unsigned
     const InstParams ip = make_params(num, t);
     out->assign(ip.off_hdr, 0);
     std::memcpy(out->data(), &ip, sizeof ip);
-    std::memcpy(out->data() + ip.off_lut, num.lut.data(), num.lut.size() * sizeof(double));
+    put_section(out, ip.off_lut, num.lut);
     return HEOM_OK;
 }
 
@@ -701,14 +712,13 @@ void pack_image(HostTables *t) {
     const size_t o = image_bytes(*t);
     t->image.assign(o, 0);
     std::memcpy(t->image.data(), &ip, sizeof ip);
-    std::memcpy(t->image.data() + ip.off_lut, t->lut.data(), t->lut.size() * sizeof(double));
-    std::memcpy(t->image.data() + ip.off_hdr, t->hdr.data(), t->hdr.size() * sizeof(PatHdr));
-    std::memcpy(t->image.data() + ip.off_cat, t->cat.data(), t->cat.size() * sizeof(CatRec));
-    std::memcpy(t->image.data() + ip.off_gidx, t->gidx.data(), t->gidx.size() * sizeof(uint32_t));
-    std::memcpy(t->image.data() + ip.off_tile, t->tiles.data(), t->tiles.size() * sizeof(TileRec));
-    std::memcpy(t->image.data() + ip.off_vrec, t->vrec.data(), t->vrec.size() * sizeof(VarRec));
-    if (!t->vloc.empty())
-        std::memcpy(t->image.data() + ip.off_vloc, t->vloc.data(), t->vloc.size() * sizeof(uint16_t));
+    put_section(&t->image, ip.off_lut, t->lut);
+    put_section(&t->image, ip.off_hdr, t->hdr);
+    put_section(&t->image, ip.off_cat, t->cat);
+    put_section(&t->image, ip.off_gidx, t->gidx);
+    put_section(&t->image, ip.off_tile, t->tiles);
+    put_section(&t->image, ip.off_vrec, t->vrec);
+    put_section(&t->image, ip.off_vloc, t->vloc);
 }
 
 }  // namespace heom

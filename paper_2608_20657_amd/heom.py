@@ -33,7 +33,7 @@ SYMBOLS = ["heom_build_tables", "heom_set_params", "heom_table_info", "heom_uplo
            "heom_set_tuning", "heom_get_tuning", "heom_work_status", "heom_params_bytes",
            "heom_upload_params", "heom_batch_create", "heom_batch_set_slot", "heom_batch_clear_slot",
            "heom_batch_device_bytes", "heom_batch_commit", "heom_batch_propagate", "heom_batch_slot_steps",
-           "heom_batch_set_graph", "heom_batch_set_merge", "heom_batch_free"]
+           "heom_batch_set_graph", "heom_batch_set_merge", "heom_batch_status", "heom_batch_free"]
 
 
 class HeomError(RuntimeError):
@@ -86,7 +86,7 @@ def _load():
         "heom_tier0_operator": [vp, dp, dp],
         "heom_tier0_expand": [vp, dp, dp],
         "heom_init_state": [vp, dp, vp, vp],
-        "heom_rhs": [vp, vp, vp, vp, ctypes.c_size_t, vp],
+        "heom_rhs": [vp, vp, vp, vp, ctypes.c_size_t, ctypes.c_int, vp],
         "heom_propagate": [vp, vp, vp, ctypes.c_size_t, ctypes.c_double, i64, i64, vp, ctypes.c_int, vp],
         "heom_observables": [vp, vp, vp, vp],
         "heom_export_layout": [vp, ctypes.POINTER(i64), ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)],
@@ -106,6 +106,7 @@ def _load():
         "heom_batch_slot_steps": [vp, ctypes.c_int32, ctypes.POINTER(i64)],
         "heom_batch_set_graph": [vp, ctypes.c_int32],
         "heom_batch_set_merge": [vp, ctypes.c_int32],
+        "heom_batch_status": [vp, ctypes.POINTER(ctypes.c_int32), ctypes.c_int32, vp],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -237,16 +238,18 @@ class Tables:
         _check(LIB.heom_init_state(self._h, t0.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), _ptr(y),
                                    _stream(stream)))
 
-    def rhs(self, y, dy, stream=None, work=None):
-        """dy = M_u y. `work`: a device buffer of at least info()['rhs_work_bytes']
-        bytes (allocated here as a uint8 tensor if None and needed)."""
-        need = self.info()["rhs_work_bytes"]
+    def rhs(self, y, dy, stream=None, work=None, precision: int = HEOM_FP64):
+        """dy = M_u y (complex128 vectors at HEOM_FP64, complex64 at HEOM_FP32,
+        HEOM_HERMITIAN OR-able). `work`: a device buffer of at least
+        info()['rhs_work_bytes'] bytes, needed without HEOM_HERMITIAN on tables
+        with transposed column targets (allocated here if None)."""
+        need = self.info()["rhs_work_bytes"] if not (precision & HEOM_HERMITIAN) else 0
         if work is None and need > 0:
             import torch
             work = torch.empty(need, dtype=torch.uint8, device=y.device)
         wbytes = work.numel() * work.element_size() if work is not None else 0
         _check(LIB.heom_rhs(self._h, _ptr(y), _ptr(dy), _ptr(work) if work is not None else None, wbytes,
-                            _stream(stream)))
+                            int(precision), _stream(stream)))
 
     def propagate(self, y, work, dt: float, nsteps: int, obs_every: int = 0, obs=None,
                   precision: int = HEOM_FP64, stream=None):
@@ -378,6 +381,17 @@ class Batch:
         max_tiles in all) as one launch per stage (0 = one launch per group).
         Takes effect at the next commit."""
         _check(LIB.heom_batch_set_merge(self._h, int(max_tiles)))
+
+    def status(self, stream=None) -> np.ndarray:
+        """Synchronize and return one flag per slot: 1 where the slot's tier-0
+        block became NaN or infinite since the last commit (heom_batch_status
+        returns E_NONFINITE then; the flags are returned instead of raising)."""
+        flags = np.zeros(self.capacity, dtype=np.int32)
+        rc = LIB.heom_batch_status(self._h, flags.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                   int(self.capacity), _stream(stream))
+        if rc not in (HEOM_OK, -5):
+            _check(rc)
+        return flags
 
     def slot_steps(self, slot: int) -> int:
         n = ctypes.c_int64()

@@ -1,4 +1,4 @@
-"""General initial density operators by linear reconstruction (Sec. VII.A).
+"""General initial density operators by linear reconstruction (Sec. VI.C).
 
 The reduced map G_t is linear in rho_S(0) (Eq. Gt-linearity) and covariant
 under molecular relabelings (Eq. Gt-covariance). Any single-excitation

@@ -3,14 +3,14 @@
 A request is one propagation: a problem (N, m, L, d, bath, eps, omega_c, g,
 kappa), a tier-0 initial block, a time step, a horizon in RK4 steps and an
 observable stride. The response is the observable trajectory on the host
-(one row of HEOM_NOBS values every `obs_every` steps, Sec. III.D).
+(one row of HEOM_NOBS values every `obs_every` steps, Sec. V.D).
 
 Device residency. Every admitted request keeps its state (16 B per unique
 variable), its work vectors (32 B per variable plus a small control area),
 its parameter block and its observable buffer in HBM until it completes.
 Requests whose structure key (min(N, L+d+2), m, L, d) agrees share one
 uploaded structure image; the unique-variable set is N-independent beyond
-that key (Sec. III.C), so only the parameter block (pool size, g, bath,
+that key (Sec. V.C.4), so only the parameter block (pool size, g, bath,
 loss) is per request. Images of keys no request uses stay cached while the
 byte budget allows and are evicted least recently used first.
 
@@ -77,6 +77,7 @@ class Result:
     obs: np.ndarray                    # (horizon // obs_every + 1, HEOM_NOBS)
     n_var: int
     lane: int = -1
+    finite: bool = True                # False if the state became NaN or infinite (heom_batch_status)
 
     @property
     def latency(self) -> float:
@@ -150,10 +151,38 @@ def plan_admission(waiting: Sequence[Tuple[int, int, int, Optional[Tuple]]], fre
     return admitted, evict
 
 
+def predicted_ms_per_step(measured_ms: Optional[float], measured_vars: int, vars_now: int) -> Optional[float]:
+    """Step time of a lane's next chunk: the last measured step time, scaled
+    up in proportion when the lane now holds more unique variables than it
+    did then (a large request joining small ones would otherwise get a chunk
+    sized for the small ones' step time, and hold back every later arrival of
+    the lane for as long). Never scaled down: a shorter chunk only costs a
+    little launch overhead."""
+    if measured_ms is None or measured_ms <= 0:
+        return None
+    if measured_vars > 0 and vars_now > measured_vars:
+        return measured_ms * (vars_now / measured_vars)
+    return measured_ms
+
+
+def hermitian_request_ok(problem, slot_matrix: Optional[np.ndarray], tol: float = 1e-12) -> bool:
+    """A request may run under HEOM_HERMITIAN only if every ADO stays
+    Hermitian: c_check_k = conj(c_k) for every channel (Eq.
+    adjoint-preservation with real rates) and a Hermitian rho_S(0), given by
+    its slot matrix (None: the photon start, which is Hermitian)."""
+    cc = problem.c_check if problem.c_check is not None else [complex(z).conjugate() for z in problem.c]
+    if not all(complex(b) == complex(a).conjugate() for a, b in zip(problem.c, cc)):
+        return False
+    if slot_matrix is None:
+        return True
+    R = np.asarray(slot_matrix)
+    return bool(np.abs(R - R.conj().T).max() <= tol * max(1.0, float(np.abs(R).max())))
+
+
 def chunk_steps(remaining: Sequence[int], ms_per_step: Optional[float], target_ms: float,
                 first: int = 8, cap: int = 4096) -> int:
     """Steps of the next chunk of a lane: about target_ms of device time at
-    the lane's measured step time, never past the nearest horizon."""
+    the lane's (predicted) step time, never past the nearest horizon."""
     if not remaining:
         return 0
     lim = min(int(r) for r in remaining)
@@ -201,6 +230,7 @@ class _Lane:
         self.active: Dict[int, _Active] = {}
         self.inflight: collections.deque = collections.deque()   # (start event, end event, steps)
         self.ms_per_step: Optional[float] = None
+        self.measured_vars = 0              # unique variables in flight when ms_per_step was measured
         self.dirty = False
         self.busy_ms = 0.0
         self.chunks = 0
@@ -248,7 +278,7 @@ class Server:
     # ---- structures
     def prepare(self, problems) -> None:
         """Build host tables for the structure keys of these problems ahead of
-        time (table construction happens before propagation, Sec. III.C)."""
+        time (table construction happens before propagation, Sec. V.C.4)."""
         for p in problems:
             self._structure(p)
 
@@ -281,6 +311,11 @@ class Server:
             self.rejected.append((req.rid, "horizon must be a positive multiple of obs_every"))
             return False
         nbytes, s = self.footprint(req)
+        if self.precision & heom.HEOM_HERMITIAN:
+            R = s.tables.tier0_expand(req.tier0) if req.tier0 is not None else None
+            if not hermitian_request_ok(req.problem, R):
+                self.rejected.append((req.rid, "HEOM_HERMITIAN needs c_check = conj(c) and a Hermitian rho_S(0)"))
+                return False
         if nbytes + s.table_bytes > self.budget:
             self.rejected.append((req.rid, "footprint exceeds the byte budget"))
             return False
@@ -354,9 +389,15 @@ class Server:
     def _retire(self, lane: _Lane) -> None:
         """Lane idle: hand back every request that reached its horizon."""
         done = [a for a in lane.active.values() if a.enqueued >= a.req.horizon]
+        if not done:
+            return
+        # slots whose state became NaN or infinite since the lane's last commit
+        flags = lane.batch.status(lane.stream) if not lane.dirty else None
         for a in done:
             obs = a.bufs[3].cpu().numpy().reshape(-1, heom.HEOM_NOBS)
-            self.results.append(Result(a.req.rid, a.req.arrival, a.admitted, self.now(), obs, a.n_var, lane.index))
+            fin = bool(np.isfinite(obs).all()) and (flags is None or flags[a.slot] == 0)
+            self.results.append(Result(a.req.rid, a.req.arrival, a.admitted, self.now(), obs, a.n_var, lane.index,
+                                       finite=fin))
             lane.batch.clear_slot(a.slot)
             lane.free.append(a.slot)
             del lane.active[a.slot]
@@ -372,7 +413,8 @@ class Server:
             lane.batch.commit(torch, lane.stream)
             lane.dirty = False
         rem = [a.req.horizon - a.enqueued for a in lane.active.values()]
-        k = chunk_steps(rem, lane.ms_per_step, self.target_ms)
+        nv = sum(a.n_var for a in lane.active.values())
+        k = chunk_steps(rem, predicted_ms_per_step(lane.ms_per_step, lane.measured_vars, nv), self.target_ms)
         if k <= 0:
             return
         e0 = torch.cuda.Event(enable_timing=True)
@@ -382,7 +424,7 @@ class Server:
         e1.record(lane.stream)
         for a in lane.active.values():
             a.enqueued += k
-        lane.inflight.append((e0, e1, k))
+        lane.inflight.append((e0, e1, k, nv))
 
     def _boundary_pending(self, lane: _Lane) -> bool:
         """True when the lane's slot set changes at the end of what is queued:
@@ -397,11 +439,12 @@ class Server:
         idle = []
         for lane in self.lanes:
             while lane.inflight and lane.inflight[0][1].query():
-                e0, e1, k = lane.inflight.popleft()
+                e0, e1, k, nv = lane.inflight.popleft()
                 ms = e0.elapsed_time(e1)
                 lane.busy_ms += ms
                 lane.chunks += 1
                 lane.ms_per_step = ms / k
+                lane.measured_vars = nv
                 progressed = True
             idle.append(not lane.inflight)
         for lane in self.lanes:
@@ -458,7 +501,7 @@ class Server:
         out = summarize(self.results, submitted, elapsed, outstanding=self.in_flight() + len(self.waiting),
                         busy_ms=[l.busy_ms for l in self.lanes])
         out.update(peak_bytes=self.peak_bytes, peak_in_flight=self.peak_in_flight, rejected=len(self.rejected),
-                   chunks=[l.chunks for l in self.lanes])
+                   chunks=[l.chunks for l in self.lanes], nonfinite=sum(1 for r in self.results if not r.finite))
         return out
 
 

@@ -111,7 +111,7 @@ CM_TO_RAD_PER_FS = 2.0 * math.pi * 2.99792458e-5   # E[cm^-1] -> omega[rad/fs]
 
 
 def config_paper_shape(N: int, d: int = 0) -> Problem:
-    """The paper's single-exponential runs (Sec. VIII), in rad/fs and fs:
+    """The paper's single-exponential runs (Sec. VII.A), in rad/fs and fs:
     omega_cav = eps = 10000 cm^-1, collective Rabi splitting 500 cm^-1 held
     fixed with g = Omega_R / (2 sqrt N) (Eq. g-fixed-Rabi), Drude-Lorentz
     bath lam = 50 cm^-1, gam = 18 cm^-1, kT = 208 cm^-1 (300 K), one
@@ -135,7 +135,7 @@ PAPER_SHAPE_DT = 0.5
 
 
 def config_paper_static(N: int, d: int = 0) -> Problem:
-    """The paper's static-disorder runs (Sec. VIII, static energetic
+    """The paper's static-disorder runs (Sec. VII.D, static energetic
     disorder), in rad/fs: Gaussian site disorder sigma = 25 cm^-1 as a
     non-decaying channel (c = sigma^2, nu = 0) beside the Drude-Lorentz
     channel of config_paper_shape (with its terminator), m = 2, L = 14,

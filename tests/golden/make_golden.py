@@ -9,7 +9,7 @@ the oracle's unique-variable generator, observables of the tier-0 block every
 Workloads:
   localized -- N=64, m=2, L=6, d=1, rho(0)=|e_1><e_1|, dt=0.02, 10000 steps
   saturated -- N=10^4, m=3, L=8, rho(0)=|+><+|, dt=0.02, 10000 steps
-  paper_n5_up -- the paper's L=25 single-exponential workload (Sec. VIII,
+  paper_n5_up -- the paper's L=25 single-exponential workload (Sec. VII.A,
       rad/fs units) at N=5, upper-polariton start, dt=0.5 fs, 400 steps
   paper_n3_superposition -- the same at N=3 with one distinguished molecule,
       rho(0) from sqrt(0.3)|e_1> + sqrt(0.7)|c>, dt=0.5 fs, 400 steps

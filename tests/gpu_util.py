@@ -63,3 +63,38 @@ def named_tier0(T, p, state: str) -> np.ndarray:
         th = 0.5 * math.atan2(2 * p.g * math.sqrt(p.N), p.omega_c - p.eps)
         return T.tier0_pure(math.cos(th), math.sin(th) / math.sqrt(p.N), [math.sin(th) / math.sqrt(p.N)] * p.d)
     raise ValueError(state)
+
+
+def mirror_permutation(S) -> np.ndarray:
+    """For every unique variable of the oracle system S, the index of the
+    entry with row and column categories exchanged (Z, P_q and T_q map to
+    themselves): the conjugate partner of the entry in a Hermitian ADO."""
+    perm = np.arange(S.n_var)
+    by_G = {}
+    for b in S.blocks:
+        by_G.setdefault(b.G, []).append(b.offset)
+    for G, offs in by_G.items():
+        G1 = G + 1
+        A, B = np.divmod(np.arange(G1 * G1), G1)
+        offs = np.asarray(offs, dtype=np.int64)[:, None]
+        perm[(offs + np.arange(G1 * G1)[None, :]).ravel()] = (offs + (B * G1 + A)[None, :]).ravel()
+    return perm
+
+
+def hermitian_vector(S, seed: int) -> np.ndarray:
+    """Seeded random state whose every ADO is Hermitian: entry (A,B) is the
+    conjugate of entry (B,A); diagonal entries and T_q are real."""
+    from paper_2608_20657_amd import workloads as W
+    y = W.random_vector(S.n_var, seed)
+    return 0.5 * (y + np.conj(y[mirror_permutation(S)]))
+
+
+def gpu_rhs_prec(T, torch, y: np.ndarray, precision: int) -> np.ndarray:
+    """heom_rhs at the given precision flags: complex128 in/out (FP64) or
+    complex64 in/out (FP32)."""
+    dt = np.complex64 if (precision & 1) else np.complex128
+    yd = torch.from_numpy(np.ascontiguousarray(y.astype(dt))).to("cuda")
+    dy = torch.empty_like(yd)
+    T.rhs(yd, dy, torch.cuda.current_stream(), precision=precision)
+    torch.cuda.synchronize()
+    return dy.cpu().numpy()

@@ -113,12 +113,29 @@ static int check(int64_t N, int m, int L, int d, int tv) {
     return 0;
 }
 
-int main() {
+int main(int argc, char **argv) {
     const int cases[][4] = {{5, 2, 3, 1}, {7, 3, 3, 0}, {4, 1, 2, 2}, {64, 2, 6, 1}, {6, 5, 2, 0}, {3, 2, 4, 1},
                             {2, 1, 3, 0}, {12, 4, 3, 0}, {40, 3, 4, 1}, {100, 3, 6, 0}, {9, 8, 2, 0}};
     for (auto &c : cases)
         for (int tv : {64, 128, 256, 512})
             if (check(c[0], c[1], c[2], c[3], tv)) return 1;
+    // seeded sweep over small structures: argv[1] = seed, argv[2] = count
+    if (argc > 2) {
+        uint64_t x = std::strtoull(argv[1], nullptr, 10) * 0x9E3779B97F4A7C15ull + 1;
+        auto next = [&](int lo, int hi) {   // xorshift64*, uniform in [lo, hi]
+            x ^= x >> 12; x ^= x << 25; x ^= x >> 27;
+            return lo + (int)(((x * 0x2545F4914F6CDD1Dull) >> 33) % (uint64_t)(hi - lo + 1));
+        };
+        const int n = std::atoi(argv[2]);
+        for (int i = 0; i < n; ++i) {
+            const int N = next(1, 30), m = next(1, 4), L = next(0, m >= 3 ? 5 : 7), d = next(0, N < 3 ? N : 3);
+            const int tv = 64 << next(0, 3);
+            if (check(N, m, L, d, tv)) {
+                std::printf("case N=%d m=%d L=%d d=%d tile=%d\n", N, m, L, d, tv);
+                return 1;
+            }
+        }
+    }
     std::printf("ok\n");
     return 0;
 }

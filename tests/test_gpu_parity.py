@@ -352,3 +352,67 @@ def test_propagate_compact_hermitian_vs_golden(name):
         assert np.abs(obs[:, j] - ref[:, j]).max() <= 1e-10 * max(np.abs(ref[:, j]).max(), 1e-300), j
     _, obs = gpu_propagate(T, torch, t0, g["dt"], g["steps"], g["every"], precision=1 | heom.HEOM_HERMITIAN)
     assert np.abs(obs[:, 1:9] - ref[:, 1:9]).max() <= 1e-5
+
+
+@pytest.mark.parametrize("N,eps,wc,g", [(5, 0.02, -0.01, 0.01), (5, -0.02, 0.01, 0.01),
+                                        (10 ** 4, 0.004, 0.0, 0.0005), (10 ** 4, 0.0, 0.004, 0.0005)])
+def test_detuned_bath_off_rabi_and_polaritons(N, eps, wc, g):
+    """Bath switched off (c = 0), cavity start, detuning of either sign: the
+    cavity population follows the detuned collective Rabi formula
+    P_cav = 1 - (W^2/(W^2 + D^2)) sin^2(sqrt(W^2 + D^2) t / 2) with
+    W = 2 g sqrt(N) (Eq. Rabi-splitting) and D = omega_c - eps, and P_+, P_-
+    stay at the weights of |c> on the upper and lower eigenvectors of the
+    cavity-bright block of H_S (numpy eigh, not the library's angle)."""
+    p = W.Problem(N=N, m=1, L=2, d=0, c=[0j], c_check=[0j], nu=[0.1], eps=eps, omega_c=wc, g=g)
+    T, torch = upload(p)
+    dt, steps, every = 0.05, 2000, 100
+    _, obs = gpu_propagate(T, torch, named_tier0(T, p, "photon"), dt, steps, every)
+    Wr, D = 2 * g * math.sqrt(N), wc - eps
+    t = np.arange(obs.shape[0]) * every * dt
+    pc = 1 - Wr ** 2 / (Wr ** 2 + D ** 2) * np.sin(0.5 * math.sqrt(Wr ** 2 + D ** 2) * t) ** 2
+    assert np.abs(obs[:, 1] - pc).max() < 1e-9
+    w, V = np.linalg.eigh(np.array([[wc, g * math.sqrt(N)], [g * math.sqrt(N), eps]]))
+    assert np.abs(obs[:, 5] - abs(V[0, 1]) ** 2).max() < 1e-10      # upper polariton
+    assert np.abs(obs[:, 6] - abs(V[0, 0]) ** 2).max() < 1e-10      # lower polariton
+    assert np.abs(obs[:, 0] - 1).max() < 1e-12
+
+
+def test_nonfinite_is_reported():
+    """An unstable time step (RK4 far outside its stability region) drives the
+    state to infinities and NaN; every kernel still exits normally, the call
+    returns, and heom_work_status reports E_NONFINITE. A stable call on the
+    same work buffer clears it."""
+    from paper_2608_20657_amd import heom
+    p = W.config_small()
+    T, torch = upload(p)
+    t0 = named_tier0(T, p, "photon")
+    with pytest.raises(heom.HeomError) as e:
+        gpu_propagate(T, torch, t0, 500.0, 300, 10)
+    assert e.value.code == -5
+    with pytest.raises(heom.HeomError) as e:               # no observables: the state's tier 0 is checked
+        gpu_propagate(T, torch, t0, 500.0, 300, 0)
+    assert e.value.code == -5
+    gpu_propagate(T, torch, t0, 0.05, 300, 10)              # finite: no error
+
+
+def test_batch_nonfinite_flags_per_slot():
+    from paper_2608_20657_amd import heom
+    torch = torch_cuda()
+    s = torch.cuda.current_stream()
+    p = W.config_small()
+    T, _ = upload(p)
+    t0 = named_tier0(T, p, "photon")
+    info = T.info()
+    b = heom.Batch(3)
+    keep = []
+    for i, dt in enumerate((0.05, 500.0, 0.05)):
+        y = torch.empty(info["n_var"], dtype=torch.complex128, device="cuda")
+        T.init_state(t0, y, s)
+        work = torch.empty(info["work_bytes_fp64"], dtype=torch.uint8, device="cuda")
+        b.set_slot(i, T, y, work, dt)
+        keep.append((y, work))
+    b.commit(torch, s)
+    assert list(b.status(s)) == [0, 0, 0]
+    b.propagate(300, 0, s)
+    assert list(b.status(s)) == [0, 1, 0]
+    assert bool(torch.isfinite(keep[0][0]).all()) and not bool(torch.isfinite(keep[1][0]).all())

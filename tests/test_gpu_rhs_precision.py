@@ -1,0 +1,129 @@
+"""heom_rhs at every precision and tile kind, element by element against the
+CPU oracle's generator M_u (Eq. uvar-propagator), through the C ABI.
+
+* HEOM_FP32 (complex64 values in and out, FP64 weights and arithmetic):
+  per element |dy - M_u y32| <= 2^-23 |M_u y32| + 1e-13 (|M_u| |y32|): one
+  rounding of the result to complex64 plus the FP64 rounding of the sum.
+* HEOM_HERMITIAN on a seeded random state whose every ADO is Hermitian:
+  mirrored column gathers (transposed tables) and compact tiles, which
+  compute each block's upper triangle and T_q and write the lower triangle as
+  conjugates. The compact cases have at least 2048 tiles, so each stage runs
+  the lower-tier launch and the top-tier kernel variant (no up moves) that
+  the benchmark times; every element of dy is checked, then sampled rows at
+  the full 17.3 M-variable structure.
+"""
+import numpy as np
+import pytest
+
+from oracle import uvar
+from paper_2608_20657_amd import workloads as W
+from tests.gpu_util import gpu_rhs_prec, hermitian_vector, rhs_bound, torch_cuda
+
+pytestmark = pytest.mark.gpu
+
+HERM = 2
+
+
+def tables(p, **tuning):
+    torch = torch_cuda()
+    from paper_2608_20657_amd import heom
+    T = heom.Tables(p)
+    if tuning:
+        T.set_tuning(**tuning)
+    buf = torch.empty(T.info()["table_bytes"], dtype=torch.uint8, device="cuda")
+    T.upload(buf, torch.cuda.current_stream())
+    return T, torch
+
+
+def fp32_bound(A, y32, want):
+    return 2.0 ** -23 * np.abs(want) + rhs_bound(A, y32)
+
+
+@pytest.mark.parametrize("N,m,L,d,cc,transposed", [(5, 2, 3, 1, True, 0), (7, 3, 3, 0, True, 1), (4, 1, 2, 2, False, 1),
+                                                   (64, 2, 6, 1, False, 0), (9, 8, 2, 0, True, 0)])
+def test_rhs_fp32_vs_oracle(N, m, L, d, cc, transposed):
+    p = W.random_problem(N, m, L, d, seed=N + 17 * m, complex_check=cc, loss=True, terminator=True)
+    T, torch = tables(p, transposed=transposed, tile_vars=64)
+    S = uvar.UVarSystem(p)
+    A = S.generator()
+    y32 = W.random_vector(S.n_var, N).astype(np.complex64).astype(np.complex128)
+    got = gpu_rhs_prec(T, torch, y32, 1).astype(np.complex128)
+    want = A @ y32
+    assert np.all(np.abs(got - want) <= fp32_bound(A, y32, want))
+
+
+@pytest.mark.parametrize("N,m,L,d,tuning", [(5, 2, 3, 1, dict(transposed=1, tile_vars=64)),
+                                            (7, 3, 3, 0, dict(compact=1, tile_vars=64)),
+                                            (4, 1, 2, 2, dict(compact=1, tile_vars=64)),
+                                            (64, 2, 6, 1, dict(compact=1, tile_vars=256)),
+                                            (6, 5, 2, 0, dict(compact=1, tile_vars=128))])
+def test_rhs_hermitian_small_vs_oracle(N, m, L, d, tuning):
+    p = W.random_problem(N, m, L, d, seed=5 * N + m, complex_check=False, loss=True, terminator=True)
+    T, torch = tables(p, **tuning)
+    S = uvar.UVarSystem(p)
+    A = S.generator()
+    y = hermitian_vector(S, seed=N + L)
+    got = gpu_rhs_prec(T, torch, y, HERM)
+    assert np.all(np.abs(got - A @ y) <= rhs_bound(A, y))
+    y32 = y.astype(np.complex64).astype(np.complex128)
+    got32 = gpu_rhs_prec(T, torch, y32, HERM | 1).astype(np.complex128)
+    want = A @ y32
+    assert np.all(np.abs(got32 - want) <= fp32_bound(A, y32, want))
+
+
+@pytest.mark.parametrize("N,m,L,tv", [(100, 4, 7, 128), (100, 3, 8, 64)])
+def test_rhs_split_top_tier_every_element(N, m, L, tv):
+    """States with >= 2048 tiles, where each stage is a lower-tier launch
+    plus the top-tier kernel variant: every element of one right-hand side
+    of a random Hermitian state against M_u y, for compact tiles (FP64 and
+    FP32), full tiles with mirrored column gathers, and the general path
+    (transposed copy of y, no Hermitian assertion)."""
+    torch_cuda()
+    p = W.random_problem(N, m, L, 0, seed=3, loss=True, terminator=True)
+    S = uvar.UVarSystem(p)
+    A = S.generator()
+    y = hermitian_vector(S, seed=N + m + L)
+    want, bound = A @ y, rhs_bound(A, y)
+    y32 = y.astype(np.complex64).astype(np.complex128)
+    want32 = A @ y32
+    for tuning, flags in ((dict(compact=1, tile_vars=tv), (HERM, HERM | 1)),
+                          (dict(compact=0, transposed=1, tile_vars=tv), (HERM, 0, 1))):
+        T, torch = tables(p, **tuning)
+        assert T.info()["n_tiles"] >= 2048
+        for fl in flags:
+            if fl & 1:
+                got32 = gpu_rhs_prec(T, torch, y32, fl).astype(np.complex128)
+                assert np.all(np.abs(got32 - want32) <= fp32_bound(A, y32, want32)), (tuning, fl)
+            else:
+                err = np.abs(gpu_rhs_prec(T, torch, y, fl) - want)
+                assert np.all(err <= bound), (tuning, fl, float((err / bound).max()))
+
+
+def test_rhs_compact_probe_sampled_rows():
+    """The benchmarked configuration itself: the 17.3 M-variable structure
+    (N=10^4, m=4, L=10) on compact 256-variable tiles under HEOM_HERMITIAN,
+    one FP64 right-hand side of a random Hermitian state; 600 sampled rows
+    (every tier, first and last blocks) against the oracle one by one."""
+    p = W.config_roofline_probe()
+    T, torch = tables(p, compact=1)
+    info = T.info()
+    assert info["n_tiles"] >= 2048 and info["compact"] == 1
+    S = uvar.UVarSystem(p)
+    assert S.n_var == info["n_var"]
+    y = hermitian_vector(S, seed=21)
+    got = gpu_rhs_prec(T, torch, y, HERM)
+    rng = np.random.default_rng(23)
+    n = S.n_var
+    # every entry of the first block of each tier, of the last blocks, plus
+    # random rows (mostly in the large top tiers)
+    first_of_tier = {}
+    for b in S.blocks:
+        first_of_tier.setdefault(b.pattern.tier, b)
+    assert sorted(first_of_tier) == list(range(p.L + 1))
+    rows = rng.choice(n, 600, replace=False).tolist() + [n - 1, n - 2] + \
+        [b.offset + j for b in list(first_of_tier.values()) + S.blocks[-3:] for j in range(b.size)]
+    ref = S.rows_at(rows)
+    for i in rows:
+        want = sum(c * y[j] for j, c in ref[i].items())
+        scale = sum(abs(c) * abs(y[j]) for j, c in ref[i].items())
+        assert abs(got[i] - want) <= 1e-13 * scale + 1e-300, i

@@ -143,16 +143,52 @@ def test_hermitian_mirror_matches_general(N, m, L, d, state, precision):
     assert np.array_equal(yn.view(np.float64), yg.view(np.float64)) and np.array_equal(on, og)
 
 
+def two_steps_from_random_hermitian(p, variants, seed=7, dt=0.02):
+    """Two RK4 steps from the same seeded random Hermitian state (every tier
+    populated, entries of order one) on several table variants; returns the
+    initial state and each variant's result (variants: (tuning, precision))."""
+    from tests.gpu_util import hermitian_vector
+    torch = torch_cuda()
+    S = uvar.UVarSystem(p)
+    y0 = hermitian_vector(S, seed)
+    s = torch.cuda.current_stream()
+    out = []
+    for tuning, prec in variants:
+        from paper_2608_20657_amd import heom
+        T = heom.Tables(p)
+        T.set_tuning(**tuning)
+        info = T.info()
+        img = torch.empty(info["table_bytes"], dtype=torch.uint8, device="cuda")
+        T.upload(img, s)
+        y = torch.from_numpy(y0).to("cuda")
+        work = torch.empty(info["work_bytes_fp64"], dtype=torch.uint8, device="cuda")
+        T.propagate(y, work, dt, 2, 0, None, prec, s)
+        T.work_status(work, s)
+        out.append(y.cpu().numpy())
+        del img, y, work
+    return y0, out
+
+
+def assert_close_per_element(a, b, y0, rel):
+    """|a - b| <= rel (|b| + |y0|) entry by entry: rounding differences of a
+    few RK4 stages from an order-one start; a wrong term of any tier moves
+    its entries by far more."""
+    err = np.abs(a - b)
+    bound = rel * (np.abs(b) + np.abs(y0))
+    assert np.all(err <= bound), f"worst ratio {(err / bound).max():.3g}"
+
+
 def test_hermitian_mirror_large_state():
+    """1.56 M variables (transposed targets by default, top tier in its own
+    launch): from a random Hermitian state, two steps with mirrored column
+    gathers equal two general steps (transposed copy) entry by entry, FP64
+    and FP32 increments."""
     from paper_2608_20657_amd import heom
     p = W.random_problem(100, 4, 8, 0, seed=3)
-    Th, torch = tables(p, -1)
-    Tg, _ = tables(p, 0)
-    t0 = named_tier0(Tg, p, "photon")
-    yg, og = gpu_propagate(Tg, torch, t0, 0.02, 6, 3, 0)
-    yh, oh = gpu_propagate(Th, torch, t0, 0.02, 6, 3, heom.HEOM_HERMITIAN)
-    assert np.abs(yh - yg).max() <= 1e-12 * np.abs(yg).max()
-    assert np.abs(oh - og).max() <= 1e-12
+    for prec, rel in ((0, 1e-12), (1, 1e-6)):
+        y0, (yg, yh) = two_steps_from_random_hermitian(
+            p, [(dict(transposed=1), prec), (dict(transposed=1), prec | heom.HEOM_HERMITIAN)])
+        assert_close_per_element(yh, yg, y0, rel)
 
 
 def test_hermitian_flag_needs_adjoint_preserving_bath():
@@ -231,17 +267,15 @@ def test_compact_matches_general(N, m, L, d, state, precision, tile_vars):
 
 
 def test_compact_large_state():
+    """1.56 M variables on compact tiles (>= 2048 tiles, split top tier): two
+    steps from a random Hermitian state equal two general steps entry by
+    entry, FP64 and FP32 increments."""
     from paper_2608_20657_amd import heom
     p = W.random_problem(100, 4, 8, 0, seed=3)
-    Tc, torch = compact_tables(p)
-    Tg, _ = tables(p, 0)
-    t0 = named_tier0(Tg, p, "photon")
-    for precision in (0, 1):
-        yg, og = gpu_propagate(Tg, torch, t0, 0.02, 6, 3, precision)
-        yc, oc = gpu_propagate(Tc, torch, t0, 0.02, 6, 3, precision | heom.HEOM_HERMITIAN)
-        tol = 1e-12 if precision == 0 else 1e-6
-        assert np.abs(yc - yg).max() <= tol * np.abs(yg).max()
-        assert np.abs(oc - og).max() <= tol
+    for prec, rel in ((0, 1e-12), (1, 1e-6)):
+        y0, (yg, yc) = two_steps_from_random_hermitian(
+            p, [(dict(transposed=1), prec), (dict(compact=1), prec | heom.HEOM_HERMITIAN)])
+        assert_close_per_element(yc, yg, y0, rel)
 
 
 def test_compact_needs_hermitian_flag():
@@ -293,26 +327,13 @@ def test_batch_compact_equals_solo():
 
 
 def test_compact_probe_size_matches_general():
-    """At the roofline probe's full size (17.3 M variables): from a Hermitian
-    state with every tier populated (3 general steps from the photon), two
-    more steps on compact tiles under HEOM_HERMITIAN equal two general steps
-    to rounding, entry by entry."""
+    """At the roofline probe's full size (17.3 M variables), the benchmarked
+    configuration: two FP64 steps on compact tiles under HEOM_HERMITIAN from a
+    random Hermitian state (every tier populated) equal two general steps
+    (full tiles, transposed copy) entry by entry."""
     from paper_2608_20657_amd import heom
-    torch = torch_cuda()
-    s = torch.cuda.current_stream()
     p = W.config_roofline_probe()
-    Tg, _ = tables(p, -1)
-    Tc, _ = compact_tables(p)
-    n = Tg.info()["n_var"]
-    y0 = torch.empty(n, dtype=torch.complex128, device="cuda")
-    Tg.init_state(Tg.tier0_pure(1.0, 0.0, []), y0, s)
-    wg = torch.empty(Tg.info()["work_bytes_fp64"], dtype=torch.uint8, device="cuda")
-    Tg.propagate(y0, wg, 0.02, 3, 0, None, 0, s)
-    yg, yc = y0.clone(), y0.clone()
-    wc = torch.empty(Tc.info()["work_bytes_fp64"], dtype=torch.uint8, device="cuda")
-    Tg.propagate(yg, wg, 0.02, 2, 0, None, 0, s)
-    Tc.propagate(yc, wc, 0.02, 2, 0, None, heom.HEOM_HERMITIAN, s)
-    torch.cuda.synchronize()
-    assert bool(torch.isfinite(yg).all()) and float(yg.abs().max()) > 0
-    err = float((yc - yg).abs().max())
-    assert err <= 1e-12 * float(yg.abs().max()), err
+    y0, (yg, yc) = two_steps_from_random_hermitian(
+        p, [(dict(transposed=1), 0), (dict(compact=1), heom.HEOM_HERMITIAN)], seed=9)
+    assert np.isfinite(yg).all()
+    assert_close_per_element(yc, yg, y0, 1e-12)

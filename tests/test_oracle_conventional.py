@@ -130,3 +130,36 @@ def test_rk4_scalar_amplification():
     R = 1 + z + z ** 2 / 2 + z ** 3 / 6 + z ** 4 / 24
     got = integrate.rk4_step(np.array([[lam]]), np.array([1.0 + 0j]), h)[0]
     assert abs(got - R) < 1e-15
+
+
+def test_terminator_pure_dephasing_closed_form():
+    """The terminator (Sec. VII.A, Ishizaki-Tanimura form) under pure
+    dephasing (g = 0): -Delta sum_i [Q_i,[Q_i, rho]] multiplies a
+    molecule-cavity coherence by exp(-Delta t) and a coherence between two
+    molecules by exp(-2 Delta t), and leaves populations alone. Against
+    X(t) = X(0) exp(-i(eps - omega_c) t - g(t) - Delta t) at N = 1 and
+    S_12(t) = S_12(0) exp(-g(t) - conj(g(t)) - 2 Delta t) at N = 2, with
+    g(t) = sum_k c_k/nu_k^2 (exp(-nu_k t) + nu_k t - 1), which the hierarchy
+    reaches to rounding at these depths."""
+    from paper_2608_20657_amd.workloads import debye_high_temperature
+    c, cc, nu = debye_high_temperature(0.02, 0.1, 0.025)
+    eps, wc, h, steps, delta = 0.01, -0.004, 0.05, 600, 0.013
+    t = steps * h
+    gt = sum(ck / nk ** 2 * (math.exp(-nk * t) + nk * t - 1.0) for ck, nk in zip(c, nu))
+    p1 = Problem(N=1, m=1, L=12, d=0, c=c, c_check=cc, nu=nu, eps=eps, omega_c=wc, g=0.0,
+                 terminator=delta)
+    rho1 = run(p1, 0.5 * np.ones((2, 2), complex), h, steps, steps)[-1]
+    want_x = 0.5 * np.exp(-1j * (eps - wc) * t - gt - delta * t)
+    assert abs(rho1[1, 0] - want_x) < 1e-9
+    assert abs(rho1[0, 1] - np.conj(want_x)) < 1e-9
+    assert abs(rho1[1, 1] - 0.5) < 1e-13 and abs(rho1[0, 0] - 0.5) < 1e-13
+    p2 = Problem(N=2, m=1, L=8, d=0, c=c, c_check=cc, nu=nu, eps=eps, omega_c=wc, g=0.0,
+                 terminator=delta)
+    psi = np.array([0.0, 1.0, 1.0]) / math.sqrt(2.0)
+    rho2 = run(p2, np.outer(psi, psi).astype(complex), h, steps, steps)[-1]
+    want_s = 0.5 * np.exp(-gt - np.conj(gt) - 2.0 * delta * t)
+    assert abs(rho2[1, 2] - want_s) < 1e-9 and abs(rho2[2, 1] - want_s) < 1e-9
+    assert abs(rho2[1, 1] - 0.5) < 1e-13 and abs(rho2[2, 2] - 0.5) < 1e-13
+    # the factor really is the terminator's: without it the same runs miss
+    # the closed form by far more than the tolerance
+    assert abs(want_x * math.exp(delta * t) - want_x) > 1e-2

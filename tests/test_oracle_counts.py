@@ -1,6 +1,6 @@
 """Pins of the oracle's pattern enumeration and unique-variable layout.
 
-Against: the paper's printed hierarchy sizes (Table I and Sec. VII.C,
+Against: the paper's printed hierarchy sizes (Table I and Sec. VII.E,
 tests/golden/table1_counts.json), the closed forms of Eqs. direct-ado-count,
 canonical-count-one, uvar-count and ordering-count, the saturation thresholds
 of Eqs. first-saturation, second-saturation and distinguished-thresholds,

@@ -90,3 +90,42 @@ def test_superposition_initial_populations(N):
     assert abs(o[4] - 0.3 * (1 - 1 / N)) < 1e-13
     assert abs(o[5] - 0.5 * (math.sqrt(0.7) + math.sqrt(0.3 / N)) ** 2) < 1e-13
     assert abs(o[6] - 0.5 * (math.sqrt(0.7) - math.sqrt(0.3 / N)) ** 2) < 1e-13
+
+
+def bath_free_hamiltonian(N, eps, wc, g):
+    """H_S of Eq. HS on {|c>, |e_1>..|e_N>}, written out here (independent
+    of the oracle's own builder)."""
+    H = np.diag([wc] + [eps] * N).astype(np.complex128)
+    H[0, 1:] = g
+    H[1:, 0] = g
+    return H
+
+
+@pytest.mark.parametrize("N,eps,wc,g", [(3, 0.05, -0.02, 0.03), (3, -0.05, 0.02, 0.03),
+                                        (5, 0.3, 0.0, 0.01), (5, 0.0, 0.3, 0.01),
+                                        (4, 0.2, -0.1, 0.2), (6, 0.0, 0.0, 0.05)])
+def test_polaritons_are_the_bright_eigenvectors(N, eps, wc, g):
+    """Eqs. Rabi-splitting and polariton-states under detuning of either
+    sign: the two eigenvectors of H_S with a cavity component are the
+    polaritons, the higher one |+>. A state prepared in the upper eigenvector
+    has P_+ = 1, P_- = 0, and in the lower one P_- = 1, P_+ = 0; the
+    compressed tier-0 form gives the same numbers. The eigenvectors come from
+    numpy's eigh, not from the oracle's angle."""
+    H = bath_free_hamiltonian(N, eps, wc, g)
+    w, V = np.linalg.eigh(H)
+    bright = [j for j in range(N + 1) if abs(V[0, j]) > 1e-8]
+    assert len(bright) == 2                       # the N-1 dark states have no cavity part
+    lo, hi = sorted(bright, key=lambda j: w[j])
+    # the splitting of the two is sqrt(Omega_R^2 + Delta^2), Omega_R = 2 g sqrt(N)
+    assert abs((w[hi] - w[lo]) - math.sqrt(4 * g * g * N + (wc - eps) ** 2)) < 1e-12
+    p = prob(N, 0, eps, wc, g)
+    S = uvar.UVarSystem(p)
+    labs = conventional.labels(N, 1, 2)
+    for j, plus in ((hi, 1.0), (lo, 0.0)):
+        v = V[:, j]
+        rho = np.outer(v, v.conj())
+        o = O.dense(rho, N, eps, wc, g)
+        assert abs(o[5] - plus) < 1e-12 and abs(o[6] - (1.0 - plus)) < 1e-12
+        assert abs(o[0] - 1.0) < 1e-12 and abs(o[3] + o[1] - 1.0) < 1e-12   # all weight in {c, B}
+        u0 = S.compress(np.r_[rho.reshape(-1), np.zeros(len(labs[1:]) * (N + 1) ** 2)], labs)
+        assert np.abs(O.from_tier0(S, u0) - o).max() < 1e-13

@@ -1,4 +1,4 @@
-"""Linear reconstruction of general initial operators (Sec. VII.A, Table II).
+"""Linear reconstruction of general initial operators (Sec. VI.C, Table II).
 
 The relabeling algebra of paper_2608_20657_amd.reconstruct is checked on the
 CPU with representative propagations run by the symmetry-adapted oracle,

@@ -1,5 +1,6 @@
 """Host-side rules of the continuous-batching server: lane choice, request
 footprints, admission against slots and a byte budget, chunk length."""
+import numpy as np
 import pytest
 
 from paper_2608_20657_amd import serve as S
@@ -106,3 +107,27 @@ def test_summarize_censors_unfinished_requests():
     assert st["p50_latency_s"] == pytest.approx(1.0)
     # all latencies: 1, 1, 10, 6 -> median 3.5
     assert st["p50_latency_all_lower_bound_s"] == pytest.approx(3.5)
+
+
+def test_predicted_step_time_scales_up_only():
+    assert S.predicted_ms_per_step(None, 0, 100) is None
+    assert S.predicted_ms_per_step(2.0, 1000, 1000) == 2.0
+    assert S.predicted_ms_per_step(2.0, 1000, 500) == 2.0          # fewer variables: keep (shorter chunks)
+    assert S.predicted_ms_per_step(2.0, 1000, 50_000) == pytest.approx(100.0)
+    # a 17 M-variable request joining small ones: its first chunk is sized
+    # for its own step time, not for 4096 small steps
+    k = S.chunk_steps([20_000], S.predicted_ms_per_step(0.02, 20_000, 17_000_000), 25.0)
+    assert k == 1
+
+
+def test_hermitian_request_rule():
+    from paper_2608_20657_amd import workloads as W
+    ok = W.random_problem(5, 2, 3, 1, seed=1, complex_check=False)
+    bad = W.random_problem(5, 2, 3, 1, seed=1, complex_check=True)
+    assert S.hermitian_request_ok(ok, None)
+    assert not S.hermitian_request_ok(bad, None)
+    R = np.array([[0.7, 0.2 + 0.1j, 0, 0], [0.2 - 0.1j, 0.3, 0, 0], [0, 0, 0, 0], [0, 0, 0, 0]])
+    assert S.hermitian_request_ok(ok, R)
+    R2 = R.copy()
+    R2[0, 1] = 0.2 - 0.1j                  # |c><e_1| coherence not matched by its adjoint
+    assert not S.hermitian_request_ok(ok, R2)

@@ -141,7 +141,7 @@ def test_too_many_categories_rejected():
 
 
 @pytest.mark.parametrize("N,d,patterns,unique", [
-    (10 ** 12, 0, 9296, 306751),     # symmetric start, saturated (Sec. VII.C)
+    (10 ** 12, 0, 9296, 306751),     # symmetric start, saturated (Sec. VII.E)
     (10 ** 12, 1, 41391, 1715600),   # one distinguished molecule, saturated
     (25, 0, 9296, 306743),
     (26, 0, 9296, 306750),
