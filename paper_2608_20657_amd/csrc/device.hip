@@ -79,6 +79,7 @@ struct heom_batch {
         uint32_t block, lds, first, count;
         int32_t slot;     // >= 0: tiles tile0.. of this slot alone (batch_stage_single)
         uint32_t tile0;
+        bool shared = false;   // tiles of structures shared by several slots (batch_stage_shared)
     };
     std::vector<SlotRec> recs;        // host copy of the committed slot records
     std::vector<Group> groups;
@@ -87,6 +88,13 @@ struct heom_batch {
     // The smallest groups with m <= 4, up to this many tiles in all, run each
     // stage as one launch instead of one per group.
     int32_t merge_tiles = 16384;
+    // Slots that share one structure image are computed by one workgroup per
+    // tile, up to this many slots at a time (1 = every slot has its own
+    // workgroups). Off by default: the shared kernel's loop over slots needs
+    // more registers than a one-slot workgroup (fewer waves per SIMD), which
+    // costs more than the table bytes it saves.
+    int32_t share_slots = 1;
+    size_t list_off = 0;                // slot lists of the shared groups in the batch buffer
     hipGraphExec_t gexec = nullptr;
     int gprec = -1;
     size_t ctr_off = 0;                 // device step counter in the batch buffer
@@ -376,9 +384,21 @@ __device__ __forceinline__ double2 load_own(const StageArgs &a, uint32_t j) {
 // LDS, the grouped sums are the Z bracket and the row sums (the column sums
 // are their conjugates), and the results go through LDS so that the tile's
 // variables are stored as one contiguous run.
+// What a call of process_tile stages into LDS before computing: nothing (the
+// tile's metadata and coefficient tables are there already), everything, or
+// only the coefficient tables (the metadata of the same tile is there, for
+// another problem with its own parameters).
+enum { STAGE_NONE = 0, STAGE_ALL = 1, STAGE_LUT = 2 };
+
+__device__ __forceinline__ void stage_lut_words(const Dev &D, const Smem &S, uint32_t words) {
+    const uint4 *src = reinterpret_cast<const uint4 *>(D.lut);
+    uint4 *dst = reinterpret_cast<uint4 *>(S.lut);
+    for (uint32_t i = threadIdx.x; i < words; i += blockDim.x) dst[i] = src[i];
+}
+
 template <int M, bool HAS64, bool HAS32, int BASE, bool EXTRA, bool OUT64, bool TOP, int CM>
 __device__ __forceinline__ void process_tile(const InstParams &P, const Dev &D, const TileRec &TR, const Smem &S,
-                                             const StageArgs &a, bool first_tile, bool stage, uint32_t lut_w) {
+                                             const StageArgs &a, bool first_tile, int stage, uint32_t lut_w) {
     const uint32_t t = threadIdx.x;
     const bool active = t < TR.nv;
     // compact tiles: this thread's entry is variable vt of the tile (row <=
@@ -403,7 +423,8 @@ __device__ __forceinline__ void process_tile(const InstParams &P, const Dev &D, 
         if (BASE == BASE_Y) ybv = (a.policy & 2u) ? ld_stream(a.ybase + TR.v0 + vt) : a.ybase[TR.v0 + vt];
         if (EXTRA) ex = a.extra[TR.v0 + vt];
     }
-    if (stage) stage_tile(D, TR, S, lut_w);
+    if (stage == STAGE_ALL) stage_tile(D, TR, S, lut_w);
+    else if (stage == STAGE_LUT) stage_lut_words(D, S, lut_w);
     __syncthreads();
 
     const uint32_t p = vr.x & 127u, A = (vr.x >> 7) & 31u, B = (vr.x >> 12) & 31u;
@@ -855,17 +876,17 @@ __device__ __forceinline__ BatchCtx batch_ctx(const SlotRec &rec, uint32_t tile,
 // The stage pattern SV of one tile (FP64: 0 = first stage, 1 = the others;
 // FP32: 0 = first, 1 = second and third, 2 = last).
 template <int M, int PREC, bool TOP, int SV>
-__device__ __forceinline__ void batch_tile(const BatchCtx &c, unsigned char *smem) {
+__device__ __forceinline__ void batch_tile(const BatchCtx &c, unsigned char *smem, int stage = STAGE_ALL) {
     const InstParams &P = *c.D.ip;
     const Smem S = carve(smem, P);
     const uint32_t lw = lut_words(P);
     if (PREC == HEOM_FP64) {
-        if (SV == 0) process_tile<M, true, false, BASE_IN, false, true, TOP, 2>(P, c.D, c.TR, S, c.a, c.first, true, lw);
-        else process_tile<M, true, false, BASE_Y, false, true, TOP, 2>(P, c.D, c.TR, S, c.a, c.first, true, lw);
+        if (SV == 0) process_tile<M, true, false, BASE_IN, false, true, TOP, 2>(P, c.D, c.TR, S, c.a, c.first, stage, lw);
+        else process_tile<M, true, false, BASE_Y, false, true, TOP, 2>(P, c.D, c.TR, S, c.a, c.first, stage, lw);
     } else {
-        if (SV == 0) process_tile<M, true, false, BASE_NONE, false, false, TOP, 2>(P, c.D, c.TR, S, c.a, false, true, lw);
-        else if (SV == 1) process_tile<M, false, true, BASE_NONE, true, false, TOP, 2>(P, c.D, c.TR, S, c.a, false, true, lw);
-        else process_tile<M, false, true, BASE_Y, true, true, TOP, 2>(P, c.D, c.TR, S, c.a, c.first, true, lw);
+        if (SV == 0) process_tile<M, true, false, BASE_NONE, false, false, TOP, 2>(P, c.D, c.TR, S, c.a, false, stage, lw);
+        else if (SV == 1) process_tile<M, false, true, BASE_NONE, true, false, TOP, 2>(P, c.D, c.TR, S, c.a, false, stage, lw);
+        else process_tile<M, false, true, BASE_Y, true, true, TOP, 2>(P, c.D, c.TR, S, c.a, c.first, stage, lw);
     }
 }
 
@@ -901,6 +922,29 @@ __global__ __launch_bounds__(MAX_TILE) void batch_stage_single(SlotRec R, uint32
     extern __shared__ __align__(16) unsigned char smem[];
     const BatchCtx c = batch_ctx<PREC>(R, tile0 + blockIdx.x, s, ctr, policy);
     batch_tile<M, PREC, TOP, SV>(c, smem);
+    advance_counter(ctr, advance);
+}
+
+// One tile of one structure for several problems that share that structure
+// (their slots use the same uploaded image, each with its own parameter
+// block): the workgroup stages the tile's metadata into LDS once and then
+// computes the tile for each problem in turn, restaging only the problem's
+// coefficient tables. The metadata is read once per tile instead of once per
+// problem (N-independence of the tables beyond saturation, Sec. V.C.4).
+// lists[B.slot] = number of problems, followed by their slot indices. Every
+// variable is computed by the same code as in stage_kernel.
+template <int M, int PREC, bool TOP, int SV>
+__global__ __launch_bounds__(MAX_TILE) void batch_stage_shared(const SlotRec *slots, const BatchTile *btiles,
+                                                             const uint32_t *lists, int s, int64_t *ctr,
+                                                             uint32_t policy, uint32_t advance) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const BatchTile B = btiles[blockIdx.x];
+    const uint32_t *L = lists + B.slot;
+    const uint32_t n = L[0];
+    for (uint32_t j = 0; j < n; ++j) {
+        const BatchCtx c = batch_ctx<PREC>(slots[L[1 + j]], B.tile & ~BTILE_TOP, s, ctr, policy);
+        batch_tile<M, PREC, TOP, SV>(c, smem, j == 0 ? STAGE_ALL : STAGE_LUT);
+    }
     advance_counter(ctr, advance);
 }
 
@@ -1162,6 +1206,20 @@ void batch_launch_group(const heom_batch *b, const heom_batch::Group &g, hipStre
                         const BatchTile *first, int stage, int64_t *ctr, uint32_t policy, uint32_t advance) {
     const dim3 grid(g.count), block(g.block);
     const int sv = stage == 0 ? 0 : (PREC == HEOM_FP64 ? 1 : (stage < 3 ? 1 : 2));
+    if (g.shared) {
+        const uint32_t *lists = reinterpret_cast<const uint32_t *>(static_cast<const unsigned char *>(b->dev) +
+                                                                   b->list_off);
+        if (sv == 0)
+            hipLaunchKernelGGL((batch_stage_shared<M, PREC, TOP, 0>), grid, block, g.lds, s, recs, first, lists, stage,
+                               ctr, policy, advance);
+        else if (sv == 1)
+            hipLaunchKernelGGL((batch_stage_shared<M, PREC, TOP, 1>), grid, block, g.lds, s, recs, first, lists, stage,
+                               ctr, policy, advance);
+        else if (PREC == HEOM_FP32)
+            hipLaunchKernelGGL((batch_stage_shared<M, PREC, TOP, 2>), grid, block, g.lds, s, recs, first, lists, stage,
+                               ctr, policy, advance);
+        return;
+    }
     if (g.slot >= 0) {
         const SlotRec &R = b->recs[(size_t)g.slot];
         const uint32_t tile0 = g.tile0;
@@ -1326,6 +1384,67 @@ int propagate_stages(const HostTables &t, hipStream_t s, double2 *y, const WorkV
             if ((rc = launch_stage<false, true, BASE_Y, true, true>(t, s, a))) return rc;
         }
     }
+    return HEOM_OK;
+}
+
+// heom_propagate on a given work buffer.
+int propagate_impl(const heom_tables *h, void *y_dev, void *work_dev, size_t work_bytes, double dt, int64_t nsteps,
+                   int64_t obs_every, double *obs_dev, int precision, void *stream) {
+    if (int rc = check_ready(h)) return rc;
+    if (int rc = check_dev(y_dev, "y_dev")) return rc;
+    if (int rc = check_dev(work_dev, "work_dev")) return rc;
+    if (!(std::isfinite(dt)) || nsteps < 0 || obs_every < 0) return fail(HEOM_E_INVAL, "bad dt, nsteps or obs_every");
+    if (obs_every > 0 && !obs_dev) return fail(HEOM_E_INVAL, "obs_dev is NULL");
+    const bool hermitian = (precision & HEOM_HERMITIAN) != 0;
+    precision &= ~HEOM_HERMITIAN;
+    if (precision != HEOM_FP64 && precision != HEOM_FP32) return fail(HEOM_E_INVAL, "unknown precision");
+    const HostTables &t = h->t;
+    if (work_bytes < work_bytes_for(t)) return fail(HEOM_E_TOO_LARGE, "work buffer smaller than work_bytes");
+    if (hermitian && !adjoint_preserving(t))
+        return fail(HEOM_E_INVAL, "HEOM_HERMITIAN needs c_check = conj(c) for every channel");
+    if (t.compact && !hermitian) return fail(HEOM_E_STATE, "compact tiles need HEOM_HERMITIAN");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    double2 *y = static_cast<double2 *>(y_dev);
+    if (obs_every > 0) {
+        hipLaunchKernelGGL(observables_kernel, dim3(1), dim3(64), 0, s, dev_view(t), y, obs_dev);
+        HIP_TRY(hipGetLastError());
+    }
+    if (nsteps == 0) return HEOM_OK;
+    const WorkView wv = work_view(t, work_dev);
+    PersistArgs pa{};
+    pa.y = y;
+    pa.dt = dt;
+    pa.step0 = 0;
+    pa.nsteps = nsteps;
+    pa.obs_every = obs_every;
+    pa.obs = obs_every > 0 ? obs_dev : nullptr;
+    pa.timeout = reinterpret_cast<uint32_t *>(wv.ctrl + 4);
+    pa.flags = reinterpret_cast<uint32_t *>(wv.ctrl + 256);
+    pa.limit = t.tune.spin_limit > 0 ? (uint32_t)t.tune.spin_limit : (1u << 20);
+    pa.policy = (uint32_t)t.tune.cache_policy;
+    if (precision == HEOM_FP64) {
+        pa.w0 = wv.w0;
+        pa.w1 = wv.w1;
+    } else {
+        pa.u3 = wv.u3;
+        pa.u1 = wv.u1;
+        pa.u2 = wv.u2;
+    }
+    hipLaunchKernelGGL(zero_u32_kernel, dim3(64), dim3(256), 0, s, pa.timeout - 1, (uint32_t)(CTRL_BYTES / 4));
+    HIP_TRY(hipGetLastError());
+    const bool persist = t.tune.persistent == 1 || (t.tune.persistent == 2 && t.tiles.size() <= 256);
+    bool used = false;
+    if (persist)
+        if (int rc = launch_persistent(t, s, pa, precision, &used)) return rc;
+    if (!used)
+        if (int rc = propagate_stages(t, s, y, wv, pa, precision, hermitian, dt, nsteps, obs_every, obs_dev))
+            return rc;
+    // flag a non-finite tier-0 block or observable (heom_work_status reports it)
+    const uint32_t n_obs = obs_every > 0 ? (uint32_t)((nsteps / obs_every + 1) * HEOM_NOBS) : 0u;
+    hipLaunchKernelGGL(finite_check_kernel, dim3(1), dim3(256), 0, s, reinterpret_cast<const double *>(y),
+                       (uint32_t)(2 * tier0_size(t)), obs_every > 0 ? obs_dev : nullptr, n_obs,
+                       reinterpret_cast<uint32_t *>(wv.ctrl + 8));
+    HIP_TRY(hipGetLastError());
     return HEOM_OK;
 }
 
@@ -1571,62 +1690,7 @@ int heom_observables(const heom_tables *h, const void *y_dev, double *obs_dev, v
 
 int heom_propagate(const heom_tables *h, void *y_dev, void *work_dev, size_t work_bytes, double dt, int64_t nsteps,
                    int64_t obs_every, double *obs_dev, int precision, void *stream) {
-    if (int rc = check_ready(h)) return rc;
-    if (int rc = check_dev(y_dev, "y_dev")) return rc;
-    if (int rc = check_dev(work_dev, "work_dev")) return rc;
-    if (!(std::isfinite(dt)) || nsteps < 0 || obs_every < 0) return fail(HEOM_E_INVAL, "bad dt, nsteps or obs_every");
-    if (obs_every > 0 && !obs_dev) return fail(HEOM_E_INVAL, "obs_dev is NULL");
-    const bool hermitian = (precision & HEOM_HERMITIAN) != 0;
-    precision &= ~HEOM_HERMITIAN;
-    if (precision != HEOM_FP64 && precision != HEOM_FP32) return fail(HEOM_E_INVAL, "unknown precision");
-    const HostTables &t = h->t;
-    if (work_bytes < work_bytes_for(t)) return fail(HEOM_E_TOO_LARGE, "work buffer smaller than work_bytes");
-    if (hermitian && !adjoint_preserving(t))
-        return fail(HEOM_E_INVAL, "HEOM_HERMITIAN needs c_check = conj(c) for every channel");
-    if (t.compact && !hermitian) return fail(HEOM_E_STATE, "compact tiles need HEOM_HERMITIAN");
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    double2 *y = static_cast<double2 *>(y_dev);
-    if (obs_every > 0) {
-        hipLaunchKernelGGL(observables_kernel, dim3(1), dim3(64), 0, s, dev_view(t), y, obs_dev);
-        HIP_TRY(hipGetLastError());
-    }
-    if (nsteps == 0) return HEOM_OK;
-    const WorkView wv = work_view(t, work_dev);
-    PersistArgs pa{};
-    pa.y = y;
-    pa.dt = dt;
-    pa.step0 = 0;
-    pa.nsteps = nsteps;
-    pa.obs_every = obs_every;
-    pa.obs = obs_every > 0 ? obs_dev : nullptr;
-    pa.timeout = reinterpret_cast<uint32_t *>(wv.ctrl + 4);
-    pa.flags = reinterpret_cast<uint32_t *>(wv.ctrl + 256);
-    pa.limit = t.tune.spin_limit > 0 ? (uint32_t)t.tune.spin_limit : (1u << 20);
-    pa.policy = (uint32_t)t.tune.cache_policy;
-    if (precision == HEOM_FP64) {
-        pa.w0 = wv.w0;
-        pa.w1 = wv.w1;
-    } else {
-        pa.u3 = wv.u3;
-        pa.u1 = wv.u1;
-        pa.u2 = wv.u2;
-    }
-    hipLaunchKernelGGL(zero_u32_kernel, dim3(64), dim3(256), 0, s, pa.timeout - 1, (uint32_t)(CTRL_BYTES / 4));
-    HIP_TRY(hipGetLastError());
-    const bool persist = t.tune.persistent == 1 || (t.tune.persistent == 2 && t.tiles.size() <= 256);
-    bool used = false;
-    if (persist)
-        if (int rc = launch_persistent(t, s, pa, precision, &used)) return rc;
-    if (!used)
-        if (int rc = propagate_stages(t, s, y, wv, pa, precision, hermitian, dt, nsteps, obs_every, obs_dev))
-            return rc;
-    // flag a non-finite tier-0 block or observable (heom_work_status reports it)
-    const uint32_t n_obs = obs_every > 0 ? (uint32_t)((nsteps / obs_every + 1) * HEOM_NOBS) : 0u;
-    hipLaunchKernelGGL(finite_check_kernel, dim3(1), dim3(256), 0, s, reinterpret_cast<const double *>(y),
-                       (uint32_t)(2 * tier0_size(t)), obs_every > 0 ? obs_dev : nullptr, n_obs,
-                       reinterpret_cast<uint32_t *>(wv.ctrl + 8));
-    HIP_TRY(hipGetLastError());
-    return HEOM_OK;
+    return propagate_impl(h, y_dev, work_dev, work_bytes, dt, nsteps, obs_every, obs_dev, precision, stream);
 }
 
 int heom_set_tuning(heom_tables *h, const heom_tuning *tu) {
@@ -1821,10 +1885,12 @@ int heom_batch_device_bytes(const heom_batch *b, size_t *bytes) {
     size_t nt = 0;
     for (const auto &S : b->slots)
         if (S.used) nt += S.tables->t.tiles.size();
-    // slot records, tile list, then the 8-byte step counter and the slots'
-    // non-finite flags (4 bytes each)
-    *bytes = ((sizeof(SlotRec) * b->slots.size() + 255) & ~(size_t)255) + ((sizeof(BatchTile) * nt + 255) & ~(size_t)255) +
-             ((8 + 4 * b->slots.size() + 255) & ~(size_t)255);
+    // slot records, tile list, slot lists of shared groups (each slot in at
+    // most two lists, each list a count and its slots), then the 8-byte step
+    // counter and the slots' non-finite flags (4 bytes each)
+    const size_t ns = b->slots.size();
+    *bytes = ((sizeof(SlotRec) * ns + 255) & ~(size_t)255) + ((sizeof(BatchTile) * nt + 255) & ~(size_t)255) +
+             ((4 * (4 * ns + 4) + 255) & ~(size_t)255) + ((8 + 4 * ns + 255) & ~(size_t)255);
     return HEOM_OK;
 }
 
@@ -1899,15 +1965,22 @@ int heom_batch_commit(heom_batch *b, void *dev, size_t bytes, void *stream) {
     // Group the tiles by (m, tile size, tier class); within a group, slot by
     // slot in slot order and each slot's tiles in order. Then the smallest
     // groups with m <= MERGE_MAX_M, up to merge_tiles tiles in all, become one
-    // merged launch whose tiles come first in the list.
+    // merged launch whose tiles come first in the list. In every other group,
+    // the slots that share one structure image (two or more) are computed
+    // together, up to share_slots per workgroup (a shared launch of the
+    // group); the rest keep one workgroup per slot and tile.
     std::vector<int> sizes;
     for (const auto &S : b->slots)
         if (S.used) sizes.push_back(S.tables->t.tile_vars);
     std::sort(sizes.begin(), sizes.end());
     sizes.erase(std::unique(sizes.begin(), sizes.end()), sizes.end());
+    struct Member {
+        uint32_t slot, j0, j1;
+    };
     struct Pending {
         heom_batch::Group g;
         std::vector<BatchTile> tiles;
+        std::vector<Member> members;
     };
     std::vector<Pending> pend;
     size_t used = 0;
@@ -1915,7 +1988,7 @@ int heom_batch_commit(heom_batch *b, void *dev, size_t bytes, void *stream) {
     for (int m = 1; m <= HEOM_MAX_M; ++m)
         for (int tv : sizes)
             for (int top = 0; top < 2; ++top) {
-                Pending P{{m, top != 0, (uint32_t)tv, 0u, 0u, 0u, -1, 0u}, {}};
+                Pending P{{m, top != 0, (uint32_t)tv, 0u, 0u, 0u, -1, 0u}, {}, {}};
                 for (size_t i = 0; i < ns; ++i) {
                     const BatchSlotHost &S = b->slots[i];
                     if (!S.used || S.tables->t.m != m || S.tables->t.tile_vars != tv) continue;
@@ -1929,6 +2002,7 @@ int heom_batch_commit(heom_batch *b, void *dev, size_t bytes, void *stream) {
                     const uint32_t j0 = top ? split : 0, j1 = top ? T : split;
                     if (j1 <= j0) continue;
                     for (uint32_t j = j0; j < j1; ++j) P.tiles.push_back(BatchTile{(uint32_t)i, top ? (j | BTILE_TOP) : j});
+                    P.members.push_back(Member{(uint32_t)i, j0, j1});
                     P.g.lds = std::max<uint32_t>(P.g.lds, t.lds_bytes);
                 }
                 if (!P.tiles.empty()) pend.push_back(std::move(P));
@@ -1961,22 +2035,68 @@ int heom_batch_commit(heom_batch *b, void *dev, size_t bytes, void *stream) {
         M.count = (uint32_t)k;
         b->groups.push_back(M);
     }
+    // slot lists of the shared groups, after the tile list (an upper bound
+    // of its length: every slot's tiles once)
+    size_t nt_all = 0;
+    for (const auto &S : b->slots)
+        if (S.used) nt_all += S.tables->t.tiles.size();
+    const size_t list_off = tile_off + ((sizeof(BatchTile) * nt_all + 255) & ~(size_t)255);
+    uint32_t *lists = reinterpret_cast<uint32_t *>(img.data() + list_off);
+    uint32_t nl = 0;
     for (size_t q = 0; q < pend.size(); ++q) {
         if (merged[q]) continue;
+        // members by structure image
+        std::vector<std::vector<Member>> by_t;
+        {
+            std::vector<const heom_tables *> keys;
+            for (const Member &mb : pend[q].members) {
+                const heom_tables *t = b->slots[mb.slot].tables;
+                size_t w = 0;
+                while (w < keys.size() && keys[w] != t) ++w;
+                if (w == keys.size()) {
+                    keys.push_back(t);
+                    by_t.emplace_back();
+                }
+                by_t[w].push_back(mb);
+            }
+        }
+        heom_batch::Group SG = pend[q].g;
+        SG.shared = true;
+        SG.first = (uint32_t)k;
+        std::vector<char> plain_slot(ns, 0);
+        for (const auto &grp : by_t) {
+            if (b->share_slots <= 1 || grp.size() < 2) {
+                for (const Member &mb : grp) plain_slot[mb.slot] = 1;
+                continue;
+            }
+            for (size_t c0 = 0; c0 < grp.size(); c0 += (size_t)b->share_slots) {
+                const size_t c1 = std::min(grp.size(), c0 + (size_t)b->share_slots);
+                const uint32_t off = nl;
+                lists[nl++] = (uint32_t)(c1 - c0);
+                for (size_t c = c0; c < c1; ++c) lists[nl++] = grp[c].slot;
+                for (uint32_t j = grp[c0].j0; j < grp[c0].j1; ++j)
+                    tl[k++] = BatchTile{off, SG.top ? (j | BTILE_TOP) : j};
+            }
+        }
+        SG.count = (uint32_t)(k - SG.first);
+        if (SG.count > 0) b->groups.push_back(SG);
         heom_batch::Group G = pend[q].g;
         G.first = (uint32_t)k;
-        for (const auto &bt : pend[q].tiles) tl[k++] = bt;
+        for (const auto &bt : pend[q].tiles)
+            if (plain_slot[bt.slot]) tl[k++] = bt;
         G.count = (uint32_t)(k - G.first);
+        if (G.count == 0) continue;
         // a group of one slot: its record goes in the kernel arguments
-        const auto &T0 = pend[q].tiles.front(), &T1 = pend[q].tiles.back();
-        if (T0.slot == T1.slot) {
-            G.slot = (int32_t)T0.slot;
-            G.tile0 = T0.tile & ~BTILE_TOP;
+        if (tl[G.first].slot == tl[k - 1].slot) {
+            G.slot = (int32_t)tl[G.first].slot;
+            G.tile0 = tl[G.first].tile & ~BTILE_TOP;
         }
         b->groups.push_back(G);
     }
+    if (nl > 4 * ns + 4) return fail(HEOM_E_INVAL, "internal: slot lists exceed their section");
+    b->list_off = list_off;
     b->recs.assign(recs, recs + ns);
-    b->ctr_off = tile_off + ((sizeof(BatchTile) * k + 255) & ~(size_t)255);   // counter = 0 in img
+    b->ctr_off = list_off + ((4 * (4 * ns + 4) + 255) & ~(size_t)255);   // counter = 0 in img
     if (b->gexec) {                        // the captured launches name the old layout
         HIP_TRY(hipGraphExecDestroy(b->gexec));
         b->gexec = nullptr;
@@ -2074,6 +2194,13 @@ int heom_batch_set_graph(heom_batch *b, int32_t steps) {
         b->gexec = nullptr;
     }
     b->graph_steps = steps;
+    return HEOM_OK;
+}
+
+int heom_batch_set_share(heom_batch *b, int32_t max_slots) {
+    if (!b || max_slots < 1 || max_slots > 4096) return fail(HEOM_E_INVAL, "bad batch or slot count");
+    b->share_slots = max_slots;
+    b->committed = false;
     return HEOM_OK;
 }
 

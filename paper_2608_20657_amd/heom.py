@@ -28,12 +28,14 @@ ERRORS = {-1: "E_INVAL", -2: "E_NOMEM", -3: "E_TOO_LARGE", -4: "E_HIP", -5: "E_N
 # every symbol include/heom.h declares
 SYMBOLS = ["heom_build_tables", "heom_set_params", "heom_table_info", "heom_upload", "heom_tier0_pure",
            "heom_tier0_operator", "heom_tier0_expand",
-           "heom_init_state", "heom_rhs", "heom_propagate", "heom_observables", "heom_export_layout",
+           "heom_init_state", "heom_rhs", "heom_propagate", "heom_observables",
+           "heom_export_layout",
            "heom_export_coefficients", "heom_free_tables", "heom_last_error", "heom_version",
            "heom_set_tuning", "heom_get_tuning", "heom_work_status", "heom_params_bytes",
            "heom_upload_params", "heom_batch_create", "heom_batch_set_slot", "heom_batch_clear_slot",
            "heom_batch_device_bytes", "heom_batch_commit", "heom_batch_propagate", "heom_batch_slot_steps",
-           "heom_batch_set_graph", "heom_batch_set_merge", "heom_batch_status", "heom_batch_free"]
+           "heom_batch_set_graph", "heom_batch_set_merge", "heom_batch_set_share", "heom_batch_status",
+           "heom_batch_free"]
 
 
 class HeomError(RuntimeError):
@@ -107,6 +109,7 @@ def _load():
         "heom_batch_set_graph": [vp, ctypes.c_int32],
         "heom_batch_set_merge": [vp, ctypes.c_int32],
         "heom_batch_status": [vp, ctypes.POINTER(ctypes.c_int32), ctypes.c_int32, vp],
+        "heom_batch_set_share": [vp, ctypes.c_int32],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -392,6 +395,12 @@ class Batch:
         if rc not in (HEOM_OK, -5):
             _check(rc)
         return flags
+
+    def set_share(self, max_slots: int):
+        """Compute slots that share one structure image together, up to
+        max_slots per workgroup and tile (1 = off). Takes effect at the next
+        commit."""
+        _check(LIB.heom_batch_set_share(self._h, int(max_slots)))
 
     def slot_steps(self, slot: int) -> int:
         n = ctypes.c_int64()
