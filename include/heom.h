@@ -219,6 +219,28 @@ int heom_propagate(const heom_tables *t, void *y_dev, void *work_dev, size_t wor
                    double dt, int64_t nsteps, int64_t obs_every, double *obs_dev,
                    int precision, void *stream);
 
+/* Bytes of the library's own work array used by heom_propagate_noalloc:
+ * 64 MiB on each GPU the library runs on, held until the process ends. Tables
+ * whose work_bytes_fp64 exceed it (about 2.09 M unique variables, or 0.84 M
+ * with transposed copies) are refused. */
+#define HEOM_NOALLOC_WORK_BYTES ((size_t)64 << 20)
+
+/* heom_propagate without a caller work buffer, for callers that cannot
+ * allocate device memory: code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation. Arguments and results as heom_propagate
+ * (the caller still passes y_dev and obs_dev); the stage vectors and the
+ * control area live in a static device array of HEOM_NOALLOC_WORK_BYTES in
+ * the library, so this call allocates nothing (no hipMalloc, no hipFree).
+ * Every call on one GPU shares that GPU's array: calls that overlap on one
+ * GPU (other streams or threads) race and must be serialized by the caller;
+ * the array keeps the last call's contents, and what must start at zero is
+ * cleared by each call with a fill kernel. heom_work_status cannot inspect
+ * this array (the caller has no pointer to it); a non-finite result shows in
+ * the observables. Errors: as heom_propagate, plus E_TOO_LARGE if the tables
+ * need more than HEOM_NOALLOC_WORK_BYTES of work memory. */
+int heom_propagate_noalloc(const heom_tables *t, void *y_dev, double dt, int64_t nsteps, int64_t obs_every,
+                           double *obs_dev, int precision, void *stream);
+
 /* Observables of the physical reduced density operator, the tier-0 block
  * (Sec. V.D, generalized to d distinguished molecules by grouping each
  * category with its multiplicity). obs_dev receives HEOM_NOBS doubles:

@@ -103,6 +103,13 @@ struct heom_batch {
     }
 };
 
+// Work memory of heom_propagate_noalloc: a file-scope device array, one copy
+// per GPU, held until the process ends. In host code `scratch` names a
+// host-side stand-in, never the device memory: its device address is looked
+// up once per device (hipGetSymbolAddress, with that device current, in
+// scratch_address below) and only that address is passed to kernels.
+static __device__ __align__(256) unsigned char scratch[HEOM_NOALLOC_WORK_BYTES];
+
 namespace {
 
 thread_local std::string g_err;
@@ -1387,7 +1394,27 @@ int propagate_stages(const HostTables &t, hipStream_t s, double2 *y, const WorkV
     return HEOM_OK;
 }
 
-// heom_propagate on a given work buffer.
+constexpr int SCRATCH_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[SCRATCH_MAX_DEVICES] = {};
+
+int scratch_address(void **out) {
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= SCRATCH_MAX_DEVICES) return fail(HEOM_E_UNSUPPORTED, "device index above 63");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return fail(HEOM_E_HIP, "hipGetSymbolAddress returned no address for the scratch array");
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return HEOM_OK;
+}
+
+// heom_propagate on a given work buffer (the caller's, or the library's
+// static scratch array for heom_propagate_noalloc).
 int propagate_impl(const heom_tables *h, void *y_dev, void *work_dev, size_t work_bytes, double dt, int64_t nsteps,
                    int64_t obs_every, double *obs_dev, int precision, void *stream) {
     if (int rc = check_ready(h)) return rc;
@@ -1691,6 +1718,17 @@ int heom_observables(const heom_tables *h, const void *y_dev, double *obs_dev, v
 int heom_propagate(const heom_tables *h, void *y_dev, void *work_dev, size_t work_bytes, double dt, int64_t nsteps,
                    int64_t obs_every, double *obs_dev, int precision, void *stream) {
     return propagate_impl(h, y_dev, work_dev, work_bytes, dt, nsteps, obs_every, obs_dev, precision, stream);
+}
+
+int heom_propagate_noalloc(const heom_tables *h, void *y_dev, double dt, int64_t nsteps, int64_t obs_every,
+                           double *obs_dev, int precision, void *stream) {
+    if (int rc = check_ready(h)) return rc;
+    if (work_bytes_for(h->t) > HEOM_NOALLOC_WORK_BYTES)
+        return fail(HEOM_E_TOO_LARGE, "the tables' work_bytes exceed HEOM_NOALLOC_WORK_BYTES (use heom_propagate "
+                                      "with a caller work buffer)");
+    void *work = nullptr;
+    if (int rc = scratch_address(&work)) return rc;
+    return propagate_impl(h, y_dev, work, HEOM_NOALLOC_WORK_BYTES, dt, nsteps, obs_every, obs_dev, precision, stream);
 }
 
 int heom_set_tuning(heom_tables *h, const heom_tuning *tu) {

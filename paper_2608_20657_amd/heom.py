@@ -22,13 +22,14 @@ HEOM_NOBS = 10
 HEOM_FP64 = 0
 HEOM_FP32 = 1
 HEOM_HERMITIAN = 2      # flag OR-ed into precision: every ADO is Hermitian
+HEOM_NOALLOC_WORK_BYTES = 64 << 20   # work memory of heom_propagate_noalloc
 ERRORS = {-1: "E_INVAL", -2: "E_NOMEM", -3: "E_TOO_LARGE", -4: "E_HIP", -5: "E_NONFINITE",
           -6: "E_UNSUPPORTED", -7: "E_STATE", -8: "E_TIMEOUT"}
 
 # every symbol include/heom.h declares
 SYMBOLS = ["heom_build_tables", "heom_set_params", "heom_table_info", "heom_upload", "heom_tier0_pure",
            "heom_tier0_operator", "heom_tier0_expand",
-           "heom_init_state", "heom_rhs", "heom_propagate", "heom_observables",
+           "heom_init_state", "heom_rhs", "heom_propagate", "heom_propagate_noalloc", "heom_observables",
            "heom_export_layout",
            "heom_export_coefficients", "heom_free_tables", "heom_last_error", "heom_version",
            "heom_set_tuning", "heom_get_tuning", "heom_work_status", "heom_params_bytes",
@@ -90,6 +91,7 @@ def _load():
         "heom_init_state": [vp, dp, vp, vp],
         "heom_rhs": [vp, vp, vp, vp, ctypes.c_size_t, ctypes.c_int, vp],
         "heom_propagate": [vp, vp, vp, ctypes.c_size_t, ctypes.c_double, i64, i64, vp, ctypes.c_int, vp],
+        "heom_propagate_noalloc": [vp, vp, ctypes.c_double, i64, i64, vp, ctypes.c_int, vp],
         "heom_observables": [vp, vp, vp, vp],
         "heom_export_layout": [vp, ctypes.POINTER(i64), ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)],
         "heom_export_coefficients": [vp, dp, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)],
@@ -260,6 +262,14 @@ class Tables:
         _check(LIB.heom_propagate(self._h, _ptr(y), _ptr(work), wbytes, float(dt), int(nsteps),
                                   int(obs_every), _ptr(obs) if obs is not None else None,
                                   int(precision), _stream(stream)))
+
+    def propagate_noalloc(self, y, dt: float, nsteps: int, obs_every: int = 0, obs=None,
+                          precision: int = HEOM_FP64, stream=None):
+        """heom_propagate with the library's static work array instead of a
+        caller buffer (allocates nothing; calls on one GPU must not overlap)."""
+        _check(LIB.heom_propagate_noalloc(self._h, _ptr(y), float(dt), int(nsteps), int(obs_every),
+                                          _ptr(obs) if obs is not None else None, int(precision),
+                                          _stream(stream)))
 
     def observables(self, y, obs, stream=None):
         _check(LIB.heom_observables(self._h, _ptr(y), _ptr(obs), _stream(stream)))
