@@ -387,8 +387,11 @@ int heom_batch_commit(heom_batch *b, void *dev, size_t bytes, void *stream);
  * of y made at the start of each call). Each problem's trajectory is bitwise the same as with
  * heom_propagate alone (no slot reads another slot's memory). precision as
  * in heom_propagate, HEOM_HERMITIAN included (E_INVAL unless every slot's
- * parameters have c_check = conj(c)). Errors: E_STATE if not committed since
- * the last change. Non-finite states are reported by heom_batch_status. */
+ * parameters have c_check = conj(c)). A batch with one occupied slot runs
+ * heom_propagate's stage launches with that slot's parameter block (unless a
+ * HIP graph replays the call, heom_batch_set_graph). Errors: E_STATE if not
+ * committed since the last change. Non-finite states are reported by
+ * heom_batch_status. */
 int heom_batch_propagate(heom_batch *b, int64_t nsteps, int precision, void *stream);
 
 /* Replay whole groups of `steps` RK4 steps from a HIP graph captured on the

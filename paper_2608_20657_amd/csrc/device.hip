@@ -1013,6 +1013,12 @@ __global__ void batch_finite_kernel(const SlotRec *slots, uint32_t *flags) {
     if (__syncthreads_or(bad) && threadIdx.x == 0) flags[blockIdx.x] = 1u;
 }
 
+// Advance a batch's device step counter by n (steps taken without the
+// batch kernels, which otherwise advance it themselves).
+__global__ void counter_add_kernel(int64_t *ctr, int64_t n) {
+    if (threadIdx.x == 0) *ctr += n;
+}
+
 __global__ void zero_kernel(double2 *y, uint32_t n) {
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
         y[i] = make_double2(0.0, 0.0);
@@ -1039,7 +1045,7 @@ __global__ void transpose_kernel(const TileRec *tiles, const VarRec *vrec, const
 constexpr uint32_t TOP_SPLIT_TILES = 2048;
 
 template <int M, bool HAS64, bool HAS32, int BASE, bool EXTRA, bool OUT64>
-void launch_m(const HostTables &t, hipStream_t s, StageArgs a) {
+void launch_m(const HostTables &t, const Dev &D, hipStream_t s, StageArgs a) {
     a.policy = (uint32_t)t.tune.cache_policy | (a.policy & 8u);
     const uint32_t T = (uint32_t)t.tiles.size();
     // Large states: the top tier (no up moves) runs in its own launch with a
@@ -1049,28 +1055,31 @@ void launch_m(const HostTables &t, hipStream_t s, StageArgs a) {
     // compact tiles (Hermitian ADOs) have kernels of their own
     if (t.compact) {
         hipLaunchKernelGGL((stage_kernel<M, HAS64, HAS32, BASE, EXTRA, OUT64, false, 1>), dim3(split),
-                           dim3(t.tile_vars), split < T ? t.lds_low : t.lds_bytes, s, dev_view(t), a,
+                           dim3(t.tile_vars), split < T ? t.lds_low : t.lds_bytes, s, D, a,
                            t.tune.xcd_map);
         if (split < T) {
             a.tile0 = split;
             hipLaunchKernelGGL((stage_kernel<M, HAS64, HAS32, BASE, EXTRA, OUT64, true, 1>), dim3(T - split),
-                               dim3(t.tile_vars), t.lds_top, s, dev_view(t), a, t.tune.xcd_map);
+                               dim3(t.tile_vars), t.lds_top, s, D, a, t.tune.xcd_map);
         }
         return;
     }
     hipLaunchKernelGGL((stage_kernel<M, HAS64, HAS32, BASE, EXTRA, OUT64, false, 0>), dim3(split),
-                       dim3(t.tile_vars), split < T ? t.lds_low : t.lds_bytes, s, dev_view(t), a, t.tune.xcd_map);
+                       dim3(t.tile_vars), split < T ? t.lds_low : t.lds_bytes, s, D, a, t.tune.xcd_map);
     if (split < T) {
         a.tile0 = split;
         hipLaunchKernelGGL((stage_kernel<M, HAS64, HAS32, BASE, EXTRA, OUT64, true, 0>), dim3(T - split),
-                           dim3(t.tile_vars), t.lds_top, s, dev_view(t), a, t.tune.xcd_map);
+                           dim3(t.tile_vars), t.lds_top, s, D, a, t.tune.xcd_map);
     }
 }
 
+// One RK4 stage of one state; D = the tables' device view, or one whose
+// parameter block is another problem's of the same structure (a batch slot).
 template <bool HAS64, bool HAS32, int BASE, bool EXTRA, bool OUT64>
-int launch_stage(const HostTables &t, hipStream_t s, const StageArgs &a) {
+int launch_stage(const HostTables &t, hipStream_t s, const StageArgs &a, const Dev *D = nullptr) {
+    const Dev Dv = D ? *D : dev_view(t);
 #define HEOM_CASE(MM) \
-    case MM: launch_m<MM, HAS64, HAS32, BASE, EXTRA, OUT64>(t, s, a); break;
+    case MM: launch_m<MM, HAS64, HAS32, BASE, EXTRA, OUT64>(t, Dv, s, a); break;
     switch (t.m) {
         HEOM_CASE(1) HEOM_CASE(2) HEOM_CASE(3) HEOM_CASE(4)
         HEOM_CASE(5) HEOM_CASE(6) HEOM_CASE(7) HEOM_CASE(8)
@@ -1334,8 +1343,12 @@ int batch_capture(heom_batch *b, hipStream_t s, int precision) {
 }
 
 // heom_propagate without the persistent kernel: one launch per RK4 stage.
+// Observable rows: row j holds the state after j*obs_every steps counted
+// from step0 (the steps taken before this call), for rows below obs_cap.
+// D: the device view (the tables' own, or a batch slot's).
 int propagate_stages(const HostTables &t, hipStream_t s, double2 *y, const WorkView &wv, const PersistArgs &pa,
-                     int precision, bool hermitian, double dt, int64_t nsteps, int64_t obs_every, double *obs_dev) {
+                     int precision, bool hermitian, double dt, int64_t nsteps, int64_t obs_every, double *obs_dev,
+                     const Dev *D = nullptr, int64_t step0 = 0, int64_t obs_cap = INT64_MAX) {
     // one launch per stage; with transposed copies, y's copy is made once
     // here and each stage then writes the copy of its own output. Hermitian
     // ADOs need no copies: column gathers read the mirrored entry.
@@ -1349,21 +1362,23 @@ int propagate_stages(const HostTables &t, hipStream_t s, double2 *y, const WorkV
     if (precision == HEOM_FP64) {
         double2 *wa = pa.w0, *wbv = pa.w1, *waT = cv.w0T, *wbT = cv.w1T;
         for (int64_t st = 1; st <= nsteps; ++st) {
-            double *ob = (obs_every > 0 && st % obs_every == 0) ? obs_dev + (st / obs_every) * HEOM_NOBS : nullptr;
+            const int64_t gs = step0 + st;
+            double *ob = (obs_every > 0 && gs % obs_every == 0 && gs / obs_every < obs_cap)
+                             ? obs_dev + (gs / obs_every) * HEOM_NOBS : nullptr;
             StageArgs a{};
             a.policy = pol;
             a.in64 = y; a.inT64 = cv.yT; a.out64 = wa; a.outT64 = waT; a.alpha = h1;
-            if ((rc = launch_stage<true, false, BASE_IN, false, true>(t, s, a))) return rc;
+            if ((rc = launch_stage<true, false, BASE_IN, false, true>(t, s, a, D))) return rc;
             a = StageArgs{}; a.policy = pol;
             a.in64 = wa; a.inT64 = waT; a.ybase = y; a.out64 = wbv; a.outT64 = wbT; a.alpha = h2;
-            if ((rc = launch_stage<true, false, BASE_Y, false, true>(t, s, a))) return rc;
+            if ((rc = launch_stage<true, false, BASE_Y, false, true>(t, s, a, D))) return rc;
             a = StageArgs{}; a.policy = pol;
             a.in64 = wbv; a.inT64 = wbT; a.ybase = y; a.out64 = wa; a.outT64 = waT; a.alpha = h3;
-            if ((rc = launch_stage<true, false, BASE_Y, false, true>(t, s, a))) return rc;
+            if ((rc = launch_stage<true, false, BASE_Y, false, true>(t, s, a, D))) return rc;
             a = StageArgs{}; a.policy = pol;
             a.in64 = wa; a.inT64 = waT; a.ybase = y; a.out64 = y; a.outT64 = cv.yT; a.alpha = h4;
             a.obs = ob;
-            if ((rc = launch_stage<true, false, BASE_Y, false, true>(t, s, a))) return rc;
+            if ((rc = launch_stage<true, false, BASE_Y, false, true>(t, s, a, D))) return rc;
         }
     } else {
         // u1 = h/4 M y, u2 = h/3 M (y + u1), u3 = h/2 M (y + u2) and
@@ -1372,23 +1387,25 @@ int propagate_stages(const HostTables &t, hipStream_t s, double2 *y, const WorkV
         float2 *u1 = pa.u1, *u2 = pa.u2, *u3 = pa.u3;
         const double inv_h1 = 1.0 / h1;
         for (int64_t st = 1; st <= nsteps; ++st) {
-            double *ob = (obs_every > 0 && st % obs_every == 0) ? obs_dev + (st / obs_every) * HEOM_NOBS : nullptr;
+            const int64_t gs = step0 + st;
+            double *ob = (obs_every > 0 && gs % obs_every == 0 && gs / obs_every < obs_cap)
+                             ? obs_dev + (gs / obs_every) * HEOM_NOBS : nullptr;
             StageArgs a{};
             a.policy = pol;
             a.in64 = y; a.inT64 = cv.yT; a.out32 = u1; a.outT32 = cv.u1T; a.alpha = h1;
-            if ((rc = launch_stage<true, false, BASE_NONE, false, false>(t, s, a))) return rc;
+            if ((rc = launch_stage<true, false, BASE_NONE, false, false>(t, s, a, D))) return rc;
             a = StageArgs{}; a.policy = pol;
             a.in32 = u1; a.inT32 = cv.u1T; a.extra = u1; a.extra_scale = inv_h1; a.out32 = u2;
             a.outT32 = cv.u2T; a.alpha = h2;
-            if ((rc = launch_stage<false, true, BASE_NONE, true, false>(t, s, a))) return rc;
+            if ((rc = launch_stage<false, true, BASE_NONE, true, false>(t, s, a, D))) return rc;
             a = StageArgs{}; a.policy = pol;
             a.in32 = u2; a.inT32 = cv.u2T; a.extra = u1; a.extra_scale = inv_h1; a.out32 = u3;
             a.outT32 = cv.u3T; a.alpha = h3;
-            if ((rc = launch_stage<false, true, BASE_NONE, true, false>(t, s, a))) return rc;
+            if ((rc = launch_stage<false, true, BASE_NONE, true, false>(t, s, a, D))) return rc;
             a = StageArgs{}; a.policy = pol;
             a.in32 = u3; a.inT32 = cv.u3T; a.extra = u1; a.extra_scale = inv_h1; a.ybase = y;
             a.out64 = y; a.outT64 = cv.yT; a.alpha = h4; a.obs = ob;
-            if ((rc = launch_stage<false, true, BASE_Y, true, true>(t, s, a))) return rc;
+            if ((rc = launch_stage<false, true, BASE_Y, true, true>(t, s, a, D))) return rc;
         }
     }
     return HEOM_OK;
@@ -2173,18 +2190,49 @@ int heom_batch_propagate(heom_batch *b, int64_t nsteps, int precision, void *str
         if ((precision & HEOM_HERMITIAN) && !S.adjoint)
             return fail(HEOM_E_INVAL, "HEOM_HERMITIAN needs c_check = conj(c) in every slot's parameters");
     }
+    int64_t done = 0;
+    // A batch of one slot (launched directly) takes heom_propagate's stage
+    // launches with the slot's parameter block: one state gains nothing from
+    // the batch kernels' slot records, which cost a little per launch.
+    size_t used = 0, only = 0;
+    for (size_t i = 0; i < b->slots.size(); ++i)
+        if (b->slots[i].used) ++used, only = i;
+    const int64_t K = b->graph_steps;
+    const bool solo = used == 1 && !(K > 0 && s != nullptr && nsteps >= K);
     // slots with transposed copies: the copy of y, made once per call
-    // (Hermitian ADOs use no copies)
-    for (size_t i = 0; i < b->slots.size(); ++i) {
+    // (Hermitian ADOs use no copies; the one-slot path makes its own)
+    for (size_t i = 0; i < b->slots.size() && !solo; ++i) {
         const BatchSlotHost &S = b->slots[i];
         if (!S.used || !S.tables->t.trcol || (precision & HEOM_HERMITIAN)) continue;
         if (int rc = launch_transpose(S.tables->t, s, b->recs[i].y, b->recs[i].yT)) return rc;
     }
-    int64_t done = 0;
+    if (solo) {
+        const BatchSlotHost &S = b->slots[only];
+        const HostTables &t = S.tables->t;
+        Dev D = dev_view(t);
+        D.ip = static_cast<const InstParams *>(b->recs[only].params ? static_cast<const void *>(b->recs[only].params)
+                                                                     : t.dev);
+        D.lut = b->recs[only].lut;
+        const WorkView wv = work_view(t, S.work);
+        PersistArgs pa{};
+        pa.w0 = wv.w0;
+        pa.w1 = wv.w1;
+        pa.u1 = wv.u1;
+        pa.u2 = wv.u2;
+        pa.u3 = wv.u3;
+        if (int rc = propagate_stages(t, s, static_cast<double2 *>(S.y), wv, pa, base_prec,
+                                      (precision & HEOM_HERMITIAN) != 0, S.dt, nsteps, S.obs_every, S.obs, &D, S.steps,
+                                      S.obs_cap))
+            return rc;
+        unsigned char *cb = static_cast<unsigned char *>(b->dev);
+        hipLaunchKernelGGL(counter_add_kernel, dim3(1), dim3(64), 0, s, reinterpret_cast<int64_t *>(cb + b->ctr_off),
+                           nsteps);
+        HIP_TRY(hipGetLastError());
+        done = nsteps;
+    }
     // Whole graphs of graph_steps steps where possible (not on the null
     // stream, which cannot be captured), single launches for the rest.
-    const int64_t K = b->graph_steps;
-    if (K > 0 && s != nullptr && nsteps >= K) {
+    if (done == 0 && K > 0 && s != nullptr && nsteps >= K) {
         if (!b->gexec || b->gprec != precision)
             if (int rc = batch_capture(b, s, precision)) return rc;
         for (; done + K <= nsteps; done += K) HIP_TRY(hipGraphLaunch(b->gexec, s));

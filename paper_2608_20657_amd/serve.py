@@ -245,7 +245,10 @@ class Server:
     precision: HEOM_FP64 or HEOM_FP32 (FP32 bulk with FP64 state), with
     HEOM_HERMITIAN OR-ed in when every request's ADOs are Hermitian (a
     Hermitian rho_S(0) and c_check = conj(c)); the structures then use
-    compact tiles (heom_tuning.compact).
+    compact tiles (heom_tuning.compact). One value, or one per lane (FP32
+    bulk pays off on large states, whose steps are bound by memory traffic;
+    small states are bound by launch latency, where FP64 steps are as fast or
+    faster). The Hermitian flag must be the same in every lane.
     target_ms: device time per chunk; sets how long an arrival waits for
     its lane's next chunk boundary."""
 
@@ -258,7 +261,14 @@ class Server:
         if len(caps) != len(self.thresholds) + 1:
             raise ValueError("one capacity per lane")
         self.lanes = [_Lane(torch, i, int(c)) for i, c in enumerate(caps)]
-        self.precision = precision
+        precs = list(precision) if isinstance(precision, (list, tuple)) else [precision] * len(self.lanes)
+        if len(precs) != len(self.lanes):
+            raise ValueError("one precision per lane")
+        if len({p & heom.HEOM_HERMITIAN for p in precs}) != 1:
+            raise ValueError("the Hermitian flag must be the same in every lane")
+        for lane, p in zip(self.lanes, precs):
+            lane.precision = int(p)
+        self.precision = int(precs[0])          # its Hermitian flag holds for every lane
         self.target_ms = float(target_ms)
         self.structs: Dict[Tuple, _Structure] = {}
         self.waiting: collections.deque = collections.deque()   # (request, lane, bytes, key)
@@ -420,7 +430,7 @@ class Server:
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
         e0.record(lane.stream)
-        lane.batch.propagate(k, self.precision, lane.stream)
+        lane.batch.propagate(k, lane.precision, lane.stream)
         e1.record(lane.stream)
         for a in lane.active.values():
             a.enqueued += k

@@ -371,3 +371,51 @@ def test_shared_structure_slots_equal_solo(share):
             for (y, obs, _), (wy, wo) in zip(keep, want):
                 assert np.array_equal(y.cpu().numpy().view(np.float64), wy.view(np.float64)), (compact, precision)
                 assert np.array_equal(obs.cpu().numpy().reshape(-1, 10), wo), (compact, precision)
+
+
+def test_one_slot_batch_across_calls_and_graph():
+    """A batch of one slot (its own parameter block, observable rows every 5
+    steps) runs heom_propagate's launches: bitwise the solo run, across calls
+    of 7 and 8 steps; then graph replays of the batch kernels continue the
+    same trajectory and rows; then a second slot joins (commit) and the first
+    keeps going, still bitwise the solo run."""
+    from paper_2608_20657_amd import heom
+    torch = torch_cuda()
+    s = torch.cuda.current_stream()
+    base = W.config_localized()
+    q = W.config_localized()
+    q.N, q.g, q.kappa = 200, 0.012, 0.002
+    T = heom.Tables(base)
+    img = torch.empty(T.info()["table_bytes"], dtype=torch.uint8, device="cuda")
+    T.upload(img, s)
+    params = torch.empty(4096 * ((T.params_bytes() + 4095) // 4096), dtype=torch.uint8, device="cuda")
+    T.upload_params(q, params, s)
+    t0 = T.tier0_pure(0.0, 0.0, [1.0])
+    info = T.info()
+    total, every = 7 + 8 + 8 + 6, 5
+    y = torch.empty(info["n_var"], dtype=torch.complex128, device="cuda")
+    T.init_state(t0, y, s)
+    work = torch.empty(info["work_bytes_fp64"], dtype=torch.uint8, device="cuda")
+    obs = torch.zeros((total // every + 1) * 10, dtype=torch.float64, device="cuda")
+    b = heom.Batch(2)
+    b.set_slot(0, T, y, work, 0.02, params=params, obs=obs, obs_every=every)
+    b.commit(torch, s)
+    b.propagate(7, 0, s)
+    b.propagate(8, 0, s)
+    b.set_graph(4)
+    b.propagate(8, 0, s)                      # two graph replays of the batch kernels
+    b.set_graph(0)
+    y2 = torch.empty(info["n_var"], dtype=torch.complex128, device="cuda")
+    T.init_state(t0, y2, s)
+    work2 = torch.empty(info["work_bytes_fp64"], dtype=torch.uint8, device="cuda")
+    b.set_slot(1, T, y2, work2, 0.02)
+    b.commit(torch, s)
+    b.propagate(6, 0, s)
+    torch.cuda.synchronize()
+    Tq = heom.Tables(q)
+    imgq = torch.empty(Tq.info()["table_bytes"], dtype=torch.uint8, device="cuda")
+    Tq.upload(imgq, s)
+    wy, wo = gpu_propagate(Tq, torch, t0, 0.02, total, every)
+    assert b.slot_steps(0) == total
+    assert np.array_equal(y.cpu().numpy().view(np.float64), wy.view(np.float64))
+    assert np.array_equal(obs.cpu().numpy().reshape(-1, 10), wo)
