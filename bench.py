@@ -187,7 +187,8 @@ def _rate(ms, n_inst, vars_total, steps):
             "rhs_updates_per_s": vars_total * 4 * steps / sec}
 
 
-def batched_section(torch, steps, warmup, n=512, seed=0, dt=0.02, flag=0, compact=False):
+def batched_section(torch, steps, warmup, n=512, seed=0, dt=0.02, flag=0, compact=False, tune_tiles=False,
+                    tune_shape=False):
     """Many independent problems at once: the batched launch (every instance
     in one launch per stage and per m) in FP64 and FP32-bulk, against the
     plain per-instance FP64 propagator called once per instance. Time per
@@ -206,6 +207,15 @@ def batched_section(torch, steps, warmup, n=512, seed=0, dt=0.02, flag=0, compac
                 structs[k].set_tuning(compact=1)
     build_s = time.perf_counter() - t0
     st = torch.cuda.current_stream()
+    tiles = {}
+    if tune_tiles:
+        # tile size per structure, by the single-problem tuner on a problem
+        # of that structure (before any parameter block is written for it)
+        from paper_2608_20657_amd import autotune
+        for k, T in structs.items():
+            r = autotune.tune_structure_tiles(T, torch, T.tier0_pure(1.0, 0.0, [0.0] * k[3]), dt, steps=10,
+                                              precision=flag)
+            tiles[str(k)] = r["best"]["tile_vars"]
     imgs = {}
     for k, T in structs.items():
         imgs[k] = torch.empty(S._round(T.info()["table_bytes"]), dtype=torch.uint8, device="cuda")
@@ -230,6 +240,11 @@ def batched_section(torch, steps, warmup, n=512, seed=0, dt=0.02, flag=0, compac
         obs_bufs.append(torch.zeros(3 * 10, dtype=torch.float64, device="cuda"))
         batch.set_slot(i, T, y, work, dt, params=params, obs=obs_bufs[-1], obs_every=warmup + steps)
     batch.commit(torch, st)
+    shape = None
+    if tune_shape:
+        from paper_2608_20657_amd import autotune
+        shape = autotune.autotune_batch(batch, torch, steps=3, precision=flag, merges=(0, 4096, 16384, 65536),
+                                        shares=(1, 2))
     out = {"workload": f"{n} independent problems drawn with seed {seed}: N~U{{4..5000}}, m~U{{1..4}}, "
                        "L~U{3..10}, g~U[0.002,0.03], lam~U[0.005,0.05], gam~U[0.02,0.2], kappa~U[0,0.02], "
                        "kT=0.025, resonant, d=0, rho(0)=|c><c|, dt=0.02",
@@ -237,7 +252,11 @@ def batched_section(torch, steps, warmup, n=512, seed=0, dt=0.02, flag=0, compac
            "largest_instance_vars": max(x[6] for x in inst),
            "median_instance_vars": int(sorted(x[6] for x in inst)[len(inst) // 2]),
            "steps": steps, "warmup": warmup, "table_build_s": round(build_s, 2), "hermitian_ados": bool(flag),
-           "table_bytes_read_per_stage": tab}
+           "table_bytes_read_per_stage": tab,
+           "tuned_tile_vars": tiles or None,
+           "tuned_launch_shape": ({"best": shape["best"], "ms_per_step": {f"merge={c['merge_tiles']},share="
+                                   f"{c['share_slots']}": round(t, 3) for c, t in shape["results"]}}
+                                  if shape else None)}
     for prec, name in ((0, "fp64_batched"), (1, "fp32_batched")):
         for q, T, params, y, work, t0v, _ in inst:
             T.init_state(t0v, y, st)
@@ -496,6 +515,10 @@ def main():
     ap.add_argument("--batched-only", action="store_true",
                     help="only the batched headline (for profiling it alone)")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--tune-tiles", action="store_true",
+                    help="tune each structure's tile size for the batched headline (before timing)")
+    ap.add_argument("--tune-batch", action="store_true",
+                    help="tune the batched headline's launch shape: merge threshold, slots per shared workgroup")
     ap.add_argument("--no-local", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--serve-rates", type=str, default="0.5:20:40,10:10:20",
@@ -549,7 +572,8 @@ def main():
         return
 
     copy_gbs = copy_bandwidth(torch)
-    bt = batched_section(torch, args.steps, args.warmup, flag=herm, compact=bool(herm))
+    bt = batched_section(torch, args.steps, args.warmup, flag=herm, compact=bool(herm), tune_tiles=args.tune_tiles,
+                         tune_shape=args.tune_batch)
     f64 = bt["fp64_batched"]
     traffic = load_traffic(PROFILE_TRAFFIC_BATCH)
     step_bytes = bt["unique_vars_total"] * stage_bytes_per_var(0) + 4 * bt["table_bytes_read_per_stage"]

@@ -349,7 +349,8 @@ class Batch:
         _check(LIB.heom_batch_create(int(capacity), ctypes.byref(h)))
         self._h = h
         self.capacity = capacity
-        self._keep = {}      # slot -> objects that must outlive the slot
+        self._keep = {}      # slot -> objects that must outlive the slot (and its obs stride)
+        self._dt = {}        # slot -> time step
         self.image = None
 
     def __del__(self):
@@ -365,11 +366,13 @@ class Batch:
         _check(LIB.heom_batch_set_slot(self._h, int(slot), tables.handle,
                                        _ptr(params) if params is not None else None, _ptr(y), _ptr(work), wbytes,
                                        float(dt), _ptr(obs) if obs is not None else None, int(obs_every), int(cap)))
-        self._keep[slot] = (tables, params, y, work, obs)
+        self._keep[slot] = (tables, params, y, work, obs, int(obs_every))
+        self._dt[slot] = float(dt)
 
     def clear_slot(self, slot: int):
         _check(LIB.heom_batch_clear_slot(self._h, int(slot)))
         self._keep.pop(slot, None)
+        self._dt.pop(slot, None)
 
     def device_bytes(self) -> int:
         n = ctypes.c_size_t()

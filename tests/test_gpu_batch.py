@@ -419,3 +419,35 @@ def test_one_slot_batch_across_calls_and_graph():
     assert b.slot_steps(0) == total
     assert np.array_equal(y.cpu().numpy().view(np.float64), wy.view(np.float64))
     assert np.array_equal(obs.cpu().numpy().reshape(-1, 10), wo)
+
+
+def test_autotune_batch_restores_states_and_keeps_results():
+    """autotune_batch tries merge thresholds and shared workgroups on the
+    committed batch, then restores every slot's state and step count: the
+    batch afterwards equals the slots' solo runs bitwise."""
+    from paper_2608_20657_amd import autotune, heom
+    torch = torch_cuda()
+    s = torch.cuda.current_stream()
+    b = heom.Batch(6)
+    keep, want = [], []
+    steps, every = 9, 3
+    for i, (N, m, L, d) in enumerate([(5, 2, 3, 1), (7, 3, 3, 0), (5, 2, 3, 1), (64, 2, 6, 1), (64, 2, 6, 1)]):
+        p = W.random_problem(N, m, L, d, seed=40 + i, loss=True)
+        T, _ = upload(p)
+        t0 = named_tier0(T, p, "site1" if d else "photon")
+        want.append(gpu_propagate(T, torch, t0, 0.02, steps, every))
+        info = T.info()
+        y = torch.empty(info["n_var"], dtype=torch.complex128, device="cuda")
+        T.init_state(t0, y, s)
+        work = torch.empty(info["work_bytes_fp64"], dtype=torch.uint8, device="cuda")
+        obs = torch.zeros((steps // every + 1) * 10, dtype=torch.float64, device="cuda")
+        b.set_slot(i, T, y, work, 0.02, obs=obs, obs_every=every)
+        keep.append((T, y, obs))
+    b.commit(torch, s)
+    res = autotune.autotune_batch(b, torch, steps=2, merges=(0, 64), shares=(1, 2))
+    assert len(res["results"]) == 4 and res["best"] in [c for c, _ in res["results"]]
+    b.propagate(steps, 0, s)
+    torch.cuda.synchronize()
+    for (T, y, obs), (wy, wo) in zip(keep, want):
+        assert np.array_equal(y.cpu().numpy().view(np.float64), wy.view(np.float64))
+        assert np.array_equal(obs.cpu().numpy().reshape(-1, 10), wo)
