@@ -178,6 +178,39 @@ def cpu_baseline(dt, var_budget, max_vars, steps=2000, local_steps=10000):
                            "seconds": round(li["seconds"], 3), "threads": li["threads"], "nnz": A.nnz})
 
 
+def cpu_configs(dt_small=0.05, dt=0.02):
+    """The compiled RK4 loop on the oracle's generator for the three
+    single-problem workloads at their full step counts on all host threads
+    (small: 2,000 steps; localized and saturated: 10^4), and on one thread
+    (the saturated workload over a 500-step prefix)."""
+    from oracle import cpu_timer, uvar
+    from paper_2608_20657_amd import workloads as W
+    exe = cpu_timer.build_timer(os.path.join(ROOT, "gpurun_out", "cpu_timer"))
+    threads = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    out = {}
+    for name, p, h, steps, one_steps, amp in (
+            ("small", W.config_small(), dt_small, 2000, 2000, lambda i: 1.0 if i == 0 else 0.0),
+            ("localized", W.config_localized(), dt, 10000, 10000, lambda i: 1.0 if i == 1 else 0.0),
+            ("saturated", W.config_saturated(), dt, 10000, 500, None)):
+        t0 = time.perf_counter()
+        S = uvar.UVarSystem(p)
+        A = S.generator()
+        if amp is None:
+            import math as _m
+            th = 0.5 * _m.atan2(2 * p.g * _m.sqrt(p.N), p.omega_c - p.eps)
+            amp = lambda i, c=_m.cos(th), s=_m.sin(th) / _m.sqrt(p.N): c if i == 0 else s
+        y0 = S.initial_state(amp=amp)
+        asm = time.perf_counter() - t0
+        _, all_ = cpu_timer.run_rk4(exe, A, y0, h, steps, threads)
+        _, one = cpu_timer.run_rk4(exe, A, y0, h, one_steps, 1)
+        out[name] = {"n_var": S.n_var, "nnz": A.nnz, "oracle_assembly_s": round(asm, 1),
+                     "all_threads": {"threads": all_["threads"], "steps": steps, "seconds": round(all_["seconds"], 3),
+                                     "updates_per_s": S.n_var * 4 * steps / all_["seconds"]},
+                     "one_thread": {"steps": one_steps, "seconds": round(one["seconds"], 3),
+                                    "updates_per_s": S.n_var * 4 * one_steps / one["seconds"]}}
+    return out
+
+
 POP_COLS = list(range(1, 9))   # every population of an observable row (cavity ... other sites)
 
 
@@ -510,6 +543,8 @@ def main():
                     help="unique variables of the batched draw in the CPU baseline's sample")
     ap.add_argument("--cpu-max-vars", type=int, default=60000)
     ap.add_argument("--cpu-steps", type=int, default=2000, help="RK4 steps per problem of that sample")
+    ap.add_argument("--cpu-configs", action="store_true",
+                    help="only the CPU baseline on the single-problem workloads at full step counts; print and exit")
     ap.add_argument("--roofline-only", action="store_true",
                     help="only the single-structure stage kernel (for profiling it alone)")
     ap.add_argument("--batched-only", action="store_true",
@@ -537,6 +572,9 @@ def main():
     ap.add_argument("--calibrate-copy-mb", type=int, default=0,
                     help="also run a plain device-to-device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
+    if args.cpu_configs:
+        print(json.dumps({"cpu_configs": cpu_configs()}), flush=True)
+        return
     if args.gpus != 1:
         print("bench.py: measures one GPU only; --gpus must be 1 (the path has no multi-GPU "
               "launch: independent problems would shard across GPUs without exchange)",

@@ -426,18 +426,18 @@ int heom_batch_set_merge(heom_batch *b, int32_t max_tiles);
  * change. */
 int heom_batch_status(const heom_batch *b, int32_t *slot_flags, int32_t cap, void *stream);
 
-/* Launch shape: slots that use the same uploaded structure (the same
- * heom_tables, each with its own parameter block) are computed by one
- * workgroup per tile, for up to max_slots slots in turn: the tile's metadata
- * (pattern headers, categories, gather lists) is staged into LDS once and
- * only each slot's coefficient tables are restaged (beyond saturation the
- * structure is N-independent, Sec. V.C.4, so problems of one structure key
- * read the same tables). 1 = one workgroup per slot and tile. Applies to the
- * groups that are not merged (heom_batch_set_merge). Default 1: the loop
- * over slots keeps more values in registers than a one-slot workgroup, so
- * fewer waves fit a SIMD, and on MI355X that costs more than the table reads
- * it saves. Results are bitwise the same either way. Takes effect at the
- * next heom_batch_commit (required). */
+/* Launch shape: with max_slots = 2, slots that use the same uploaded
+ * structure (the same heom_tables, each with its own parameter block) are
+ * computed in pairs, side by side in one workgroup of twice the tile size:
+ * each half computes the tile for one slot, and the tile's metadata (pattern
+ * headers, categories, gather lists) is staged into LDS once for both
+ * (beyond saturation the structure is N-independent, Sec. V.C.4, so problems
+ * of one structure key read the same tables). Structures with 512-variable
+ * tiles, or whose pair would need more than 64 KiB of LDS, and an odd slot
+ * out keep one workgroup per slot. 1 = off (default). Applies to the groups
+ * that are not merged (heom_batch_set_merge). Results are bitwise the same
+ * either way. Takes effect at the next heom_batch_commit (required). Errors:
+ * E_INVAL unless max_slots is 1 or 2. */
 int heom_batch_set_share(heom_batch *b, int32_t max_slots);
 
 /* Steps a slot has taken since it was set. */

@@ -88,11 +88,9 @@ struct heom_batch {
     // The smallest groups with m <= 4, up to this many tiles in all, run each
     // stage as one launch instead of one per group.
     int32_t merge_tiles = 16384;
-    // Slots that share one structure image are computed by one workgroup per
-    // tile, up to this many slots at a time (1 = every slot has its own
-    // workgroups). Off by default: the shared kernel's loop over slots needs
-    // more registers than a one-slot workgroup (fewer waves per SIMD), which
-    // costs more than the table bytes it saves.
+    // Slots that share one structure image: 2 = computed in pairs, side by
+    // side in one workgroup per tile (batch_stage_pair), 1 = every slot has
+    // its own workgroups.
     int32_t share_slots = 1;
     size_t list_off = 0;                // slot lists of the shared groups in the batch buffer
     hipGraphExec_t gexec = nullptr;
@@ -297,6 +295,28 @@ __device__ __forceinline__ Smem carve(unsigned char *smem, const InstParams &P) 
     return S;
 }
 
+// LDS of a workgroup holding two problems of one structure: the shared
+// metadata (headers, categories, gather indices for max_ng), then per half
+// the tile values and grouped sums, coefficient tables and multiplicities.
+__host__ __device__ __forceinline__ uint32_t pair_shared_bytes(const InstParams &P) {
+    return 32u * P.max_np + 16u * P.max_nc + 4u * ((P.max_ng + 3u) & ~3u);
+}
+__host__ __device__ __forceinline__ uint32_t pair_half_bytes(const InstParams &P) {
+    return 32u * P.val_len + 16u * (uint32_t)P.m * (uint32_t)(P.L + 1) + 8u * ((P.max_nc + 1u) & ~1u);
+}
+__device__ __forceinline__ Smem carve_pair(unsigned char *smem, const InstParams &P, uint32_t half) {
+    Smem S;
+    S.hdr = reinterpret_cast<PatHdr *>(smem);
+    S.cat = reinterpret_cast<CatRec *>(S.hdr + P.max_np);
+    S.gix = reinterpret_cast<uint32_t *>(S.cat + P.max_nc);
+    unsigned char *h = smem + pair_shared_bytes(P) + half * pair_half_bytes(P);
+    S.val = reinterpret_cast<double2 *>(h);
+    S.rc = S.val + P.val_len;
+    S.lut = reinterpret_cast<double *>(h + 32u * P.val_len);
+    S.md = S.lut + 2u * (uint32_t)P.m * (uint32_t)(P.L + 1);
+    return S;
+}
+
 // Copy a tile's metadata (pattern headers, categories, gather indices) and,
 // if lut_words > 0, the coefficient tables into LDS, as 16-byte words. The
 // four sources are one index range, and each thread issues its loads (two
@@ -395,7 +415,11 @@ __device__ __forceinline__ double2 load_own(const StageArgs &a, uint32_t j) {
 // tile's metadata and coefficient tables are there already), everything, or
 // only the coefficient tables (the metadata of the same tile is there, for
 // another problem with its own parameters).
-enum { STAGE_NONE = 0, STAGE_ALL = 1, STAGE_LUT = 2 };
+// STAGE_PAIR: two problems of the same structure side by side in one
+// workgroup (each half of the threads computes one of them): the tile's
+// metadata is staged once by all threads, each half stages its problem's
+// coefficient tables into its own LDS region.
+enum { STAGE_NONE = 0, STAGE_ALL = 1, STAGE_LUT = 2, STAGE_PAIR = 3 };
 
 __device__ __forceinline__ void stage_lut_words(const Dev &D, const Smem &S, uint32_t words) {
     const uint4 *src = reinterpret_cast<const uint4 *>(D.lut);
@@ -403,10 +427,14 @@ __device__ __forceinline__ void stage_lut_words(const Dev &D, const Smem &S, uin
     for (uint32_t i = threadIdx.x; i < words; i += blockDim.x) dst[i] = src[i];
 }
 
+// tbase, tcount: the threads that compute this problem (all of the block,
+// or one half of it for STAGE_PAIR).
 template <int M, bool HAS64, bool HAS32, int BASE, bool EXTRA, bool OUT64, bool TOP, int CM>
 __device__ __forceinline__ void process_tile(const InstParams &P, const Dev &D, const TileRec &TR, const Smem &S,
-                                             const StageArgs &a, bool first_tile, int stage, uint32_t lut_w) {
-    const uint32_t t = threadIdx.x;
+                                             const StageArgs &a, bool first_tile, int stage, uint32_t lut_w,
+                                             uint32_t tbase = 0u, uint32_t tcount = 0u) {
+    const uint32_t t = threadIdx.x - tbase;
+    const uint32_t tn = tcount ? tcount : blockDim.x;
     const bool active = t < TR.nv;
     // compact tiles: this thread's entry is variable vt of the tile (row <=
     // column or a T_q); it also owns the mirrored entry, the conjugate.
@@ -432,6 +460,12 @@ __device__ __forceinline__ void process_tile(const InstParams &P, const Dev &D, 
     }
     if (stage == STAGE_ALL) stage_tile(D, TR, S, lut_w);
     else if (stage == STAGE_LUT) stage_lut_words(D, S, lut_w);
+    else if (stage == STAGE_PAIR) {
+        stage_tile(D, TR, S, 0u);            // the shared metadata, by every thread of the block
+        const uint4 *src = reinterpret_cast<const uint4 *>(D.lut);
+        uint4 *dst = reinterpret_cast<uint4 *>(S.lut);
+        for (uint32_t i = t; i < lut_w; i += tn) dst[i] = src[i];
+    }
     __syncthreads();
 
     const uint32_t p = vr.x & 127u, A = (vr.x >> 7) & 31u, B = (vr.x >> 12) & 31u;
@@ -622,7 +656,7 @@ __device__ __forceinline__ void process_tile(const InstParams &P, const Dev &D, 
         __syncthreads();
         const PatHdr HL = S.hdr[TR.np - 1];
         const uint32_t nfull = HL.off + HL.size - TR.v0;
-        for (uint32_t i = t; i < nfull; i += blockDim.x) {
+        for (uint32_t i = t; i < nfull; i += tn) {
             const double2 r = S.val[i];
             if (a.policy & 4u) {
                 if (OUT64) st_stream(a.out64 + TR.v0 + i, r);
@@ -633,14 +667,16 @@ __device__ __forceinline__ void process_tile(const InstParams &P, const Dev &D, 
             }
         }
     }
-    if (a.obs != nullptr && first_tile) {
-        // the empty pattern is the first block of tile 0: evaluate the
-        // observables of the freshly computed tier-0 block (compact tiles
-        // hold it in LDS already)
+    // the empty pattern is the first block of tile 0: evaluate the
+    // observables of the freshly computed tier-0 block (compact tiles hold it
+    // in LDS already). With two problems in the block, both halves take the
+    // barriers whether or not their problem samples observables now.
+    const bool obs_here = a.obs != nullptr && first_tile;
+    if (stage == STAGE_PAIR ? first_tile : obs_here) {
         const uint32_t n0 = S.hdr[0].size;
-        if (!cmp && active && vt < n0) S.val[vt] = res;
+        if (obs_here && !cmp && active && vt < n0) S.val[vt] = res;
         __syncthreads();
-        if (t == 0) tier0_observables(P, S.hdr[0], S.cat, S.val, a.obs);
+        if (obs_here && t == 0) tier0_observables(P, S.hdr[0], S.cat, S.val, a.obs);
         __syncthreads();
     }
 }
@@ -932,25 +968,35 @@ __global__ __launch_bounds__(MAX_TILE) void batch_stage_single(SlotRec R, uint32
     advance_counter(ctr, advance);
 }
 
-// One tile of one structure for several problems that share that structure
+// One tile of one structure for two problems that share that structure
 // (their slots use the same uploaded image, each with its own parameter
-// block): the workgroup stages the tile's metadata into LDS once and then
-// computes the tile for each problem in turn, restaging only the problem's
-// coefficient tables. The metadata is read once per tile instead of once per
-// problem (N-independence of the tables beyond saturation, Sec. V.C.4).
-// lists[B.slot] = number of problems, followed by their slot indices. Every
-// variable is computed by the same code as in stage_kernel.
+// block), side by side: the block has twice the tile's threads, each half
+// computes the tile for one problem, and the tile's metadata is staged into
+// LDS once for both (N-independence of the tables beyond saturation, Sec.
+// V.C.4). lists[B.slot] = 2, followed by the two slot indices. Every thread
+// runs the same code as in a one-problem workgroup (same registers); every
+// variable is computed as in stage_kernel.
 template <int M, int PREC, bool TOP, int SV>
-__global__ __launch_bounds__(MAX_TILE) void batch_stage_shared(const SlotRec *slots, const BatchTile *btiles,
-                                                             const uint32_t *lists, int s, int64_t *ctr,
-                                                             uint32_t policy, uint32_t advance) {
+__global__ __launch_bounds__(MAX_TILE) void batch_stage_pair(const SlotRec *slots, const BatchTile *btiles,
+                                                           const uint32_t *lists, int s, int64_t *ctr,
+                                                           uint32_t policy, uint32_t advance) {
     extern __shared__ __align__(16) unsigned char smem[];
     const BatchTile B = btiles[blockIdx.x];
-    const uint32_t *L = lists + B.slot;
-    const uint32_t n = L[0];
-    for (uint32_t j = 0; j < n; ++j) {
-        const BatchCtx c = batch_ctx<PREC>(slots[L[1 + j]], B.tile & ~BTILE_TOP, s, ctr, policy);
-        batch_tile<M, PREC, TOP, SV>(c, smem, j == 0 ? STAGE_ALL : STAGE_LUT);
+    const uint32_t tv = blockDim.x / 2u;
+    // each wave lies in one half (tv is a multiple of the wave size)
+    const uint32_t half = __builtin_amdgcn_readfirstlane(threadIdx.x / tv);
+    const uint32_t slot = __builtin_amdgcn_readfirstlane(lists[B.slot + 1u + half]);
+    const BatchCtx c = batch_ctx<PREC>(slots[slot], B.tile & ~BTILE_TOP, s, ctr, policy);
+    const InstParams &P = *c.D.ip;
+    const Smem S = carve_pair(smem, P, half);
+    const uint32_t lw = lut_words(P), tb = half * tv;
+    if (PREC == HEOM_FP64) {
+        if (SV == 0) process_tile<M, true, false, BASE_IN, false, true, TOP, 2>(P, c.D, c.TR, S, c.a, c.first, STAGE_PAIR, lw, tb, tv);
+        else process_tile<M, true, false, BASE_Y, false, true, TOP, 2>(P, c.D, c.TR, S, c.a, c.first, STAGE_PAIR, lw, tb, tv);
+    } else {
+        if (SV == 0) process_tile<M, true, false, BASE_NONE, false, false, TOP, 2>(P, c.D, c.TR, S, c.a, false, STAGE_PAIR, lw, tb, tv);
+        else if (SV == 1) process_tile<M, false, true, BASE_NONE, true, false, TOP, 2>(P, c.D, c.TR, S, c.a, false, STAGE_PAIR, lw, tb, tv);
+        else process_tile<M, false, true, BASE_Y, true, true, TOP, 2>(P, c.D, c.TR, S, c.a, c.first, STAGE_PAIR, lw, tb, tv);
     }
     advance_counter(ctr, advance);
 }
@@ -1220,19 +1266,19 @@ int check_dev(const void *p, const char *name) {
 template <int M, int PREC, bool TOP>
 void batch_launch_group(const heom_batch *b, const heom_batch::Group &g, hipStream_t s, const SlotRec *recs,
                         const BatchTile *first, int stage, int64_t *ctr, uint32_t policy, uint32_t advance) {
-    const dim3 grid(g.count), block(g.block);
+    const dim3 grid(g.count), block(g.shared ? 2u * g.block : g.block);
     const int sv = stage == 0 ? 0 : (PREC == HEOM_FP64 ? 1 : (stage < 3 ? 1 : 2));
     if (g.shared) {
         const uint32_t *lists = reinterpret_cast<const uint32_t *>(static_cast<const unsigned char *>(b->dev) +
                                                                    b->list_off);
         if (sv == 0)
-            hipLaunchKernelGGL((batch_stage_shared<M, PREC, TOP, 0>), grid, block, g.lds, s, recs, first, lists, stage,
+            hipLaunchKernelGGL((batch_stage_pair<M, PREC, TOP, 0>), grid, block, g.lds, s, recs, first, lists, stage,
                                ctr, policy, advance);
         else if (sv == 1)
-            hipLaunchKernelGGL((batch_stage_shared<M, PREC, TOP, 1>), grid, block, g.lds, s, recs, first, lists, stage,
+            hipLaunchKernelGGL((batch_stage_pair<M, PREC, TOP, 1>), grid, block, g.lds, s, recs, first, lists, stage,
                                ctr, policy, advance);
         else if (PREC == HEOM_FP32)
-            hipLaunchKernelGGL((batch_stage_shared<M, PREC, TOP, 2>), grid, block, g.lds, s, recs, first, lists, stage,
+            hipLaunchKernelGGL((batch_stage_pair<M, PREC, TOP, 2>), grid, block, g.lds, s, recs, first, lists, stage,
                                ctr, policy, advance);
         return;
     }
@@ -2021,9 +2067,9 @@ int heom_batch_commit(heom_batch *b, void *dev, size_t bytes, void *stream) {
     // slot in slot order and each slot's tiles in order. Then the smallest
     // groups with m <= MERGE_MAX_M, up to merge_tiles tiles in all, become one
     // merged launch whose tiles come first in the list. In every other group,
-    // the slots that share one structure image (two or more) are computed
-    // together, up to share_slots per workgroup (a shared launch of the
-    // group); the rest keep one workgroup per slot and tile.
+    // with share_slots = 2, the slots that share one structure image are
+    // computed in pairs (a shared launch of the group); the rest keep one
+    // workgroup per slot and tile.
     std::vector<int> sizes;
     for (const auto &S : b->slots)
         if (S.used) sizes.push_back(S.tables->t.tile_vars);
@@ -2117,21 +2163,27 @@ int heom_batch_commit(heom_batch *b, void *dev, size_t bytes, void *stream) {
         }
         heom_batch::Group SG = pend[q].g;
         SG.shared = true;
+        SG.lds = 0;
         SG.first = (uint32_t)k;
         std::vector<char> plain_slot(ns, 0);
+        // pairs of slots on one structure image (workgroups of twice the
+        // tile size, so tiles of at most MAX_TILE / 2 variables); an odd slot
+        // out keeps one-slot workgroups
         for (const auto &grp : by_t) {
-            if (b->share_slots <= 1 || grp.size() < 2) {
-                for (const Member &mb : grp) plain_slot[mb.slot] = 1;
-                continue;
-            }
-            for (size_t c0 = 0; c0 < grp.size(); c0 += (size_t)b->share_slots) {
-                const size_t c1 = std::min(grp.size(), c0 + (size_t)b->share_slots);
+            const InstParams *ip0 = reinterpret_cast<const InstParams *>(b->slots[grp[0].slot].tables->t.image.data());
+            const bool fits = pend[q].g.block * 2u <= (uint32_t)MAX_TILE &&
+                              pair_shared_bytes(*ip0) + 2u * pair_half_bytes(*ip0) <= 64u * 1024u;
+            const size_t pairs = (b->share_slots >= 2 && fits) ? grp.size() / 2 : 0;
+            for (size_t c = 2 * pairs; c < grp.size(); ++c) plain_slot[grp[c].slot] = 1;
+            for (size_t c = 0; c < pairs; ++c) {
                 const uint32_t off = nl;
-                lists[nl++] = (uint32_t)(c1 - c0);
-                for (size_t c = c0; c < c1; ++c) lists[nl++] = grp[c].slot;
-                for (uint32_t j = grp[c0].j0; j < grp[c0].j1; ++j)
+                lists[nl++] = 2u;
+                lists[nl++] = grp[2 * c].slot;
+                lists[nl++] = grp[2 * c + 1].slot;
+                for (uint32_t j = grp[2 * c].j0; j < grp[2 * c].j1; ++j)
                     tl[k++] = BatchTile{off, SG.top ? (j | BTILE_TOP) : j};
             }
+            if (pairs > 0) SG.lds = std::max<uint32_t>(SG.lds, pair_shared_bytes(*ip0) + 2u * pair_half_bytes(*ip0));
         }
         SG.count = (uint32_t)(k - SG.first);
         if (SG.count > 0) b->groups.push_back(SG);
@@ -2284,7 +2336,7 @@ int heom_batch_set_graph(heom_batch *b, int32_t steps) {
 }
 
 int heom_batch_set_share(heom_batch *b, int32_t max_slots) {
-    if (!b || max_slots < 1 || max_slots > 4096) return fail(HEOM_E_INVAL, "bad batch or slot count");
+    if (!b || max_slots < 1 || max_slots > 2) return fail(HEOM_E_INVAL, "bad batch, or slots per workgroup not 1 or 2");
     b->share_slots = max_slots;
     b->committed = false;
     return HEOM_OK;

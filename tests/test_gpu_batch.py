@@ -314,13 +314,14 @@ def test_hermitian_flag_checked_per_slot():
     torch.cuda.synchronize()
 
 
-@pytest.mark.parametrize("share", [1, 2, 8])
+@pytest.mark.parametrize("share", [1, 2])
 def test_shared_structure_slots_equal_solo(share):
     """Slots on one uploaded structure with their own parameter blocks
-    (different N beyond saturation, couplings, loss), computed by shared
-    workgroups (one tile's metadata staged once for up to `share` slots),
-    beside slots of another structure: every slot equals its heom_propagate
-    run bitwise, FP64 and FP32 increments, plain and compact tiles."""
+    (different N beyond saturation, couplings, loss; every other slot without
+    observables), computed in pairs side by side (one tile's metadata staged
+    once for both halves of a workgroup) with an odd slot out, beside slots
+    of another structure: every slot equals its heom_propagate run bitwise,
+    FP64 and FP32 increments, plain and compact tiles."""
     from paper_2608_20657_amd import heom
     torch = torch_cuda()
     s = torch.cuda.current_stream()
@@ -355,15 +356,17 @@ def test_shared_structure_slots_equal_solo(share):
                     y = torch.empty(info["n_var"], dtype=torch.complex128, device="cuda")
                     T.init_state(t0, y, s)
                     work = torch.empty(info["work_bytes_fp64"], dtype=torch.uint8, device="cuda")
+                    ev = every if slot % 2 == 0 else 0
                     obs = torch.zeros((steps // every + 1) * 10, dtype=torch.float64, device="cuda")
-                    b.set_slot(slot, T, y, work, dt, params=params, obs=obs, obs_every=every)
+                    b.set_slot(slot, T, y, work, dt, params=params, obs=obs if ev else None, obs_every=ev)
                     keep.append((y, obs, params))
                     # solo: the same problem on its own tables
                     Ts = heom.Tables(q)
                     Ts.set_tuning(compact=compact)
                     imgs = torch.empty(Ts.info()["table_bytes"], dtype=torch.uint8, device="cuda")
                     Ts.upload(imgs, s)
-                    want.append(gpu_propagate(Ts, torch, t0, dt, steps, every, flag))
+                    wy, wo = gpu_propagate(Ts, torch, t0, dt, steps, ev, flag)
+                    want.append((wy, wo if ev else np.zeros((steps // every + 1, 10))))
                     slot += 1
             b.commit(torch, s)
             b.propagate(steps, flag, s)
