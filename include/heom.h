@@ -277,7 +277,9 @@ typedef struct heom_tuning {
                                 grid barrier after each stage (check heom_work_status afterwards:
                                 a barrier that times out leaves the state mid-step); 0 (default):
                                 one launch per stage; 2: persistent when the state has at most
-                                256 tiles */
+                                256 tiles; 3: persistent, the grid barrier counting arrivals in
+                                per-group counters instead of every workgroup polling every
+                                workgroup's flag */
     int32_t xcd_map;         /* 1: map workgroups to tiles so each XCD streams a contiguous run */
     int32_t max_workgroups;  /* cap on resident workgroups of the persistent launch (0 = occupancy limit) */
     int32_t spin_limit;      /* polls before a grid barrier gives up (0 = default, about 4 s) */

@@ -731,6 +731,38 @@ __device__ __forceinline__ bool grid_barrier(uint32_t *flags, uint32_t *timeout,
     return ok;
 }
 
+// The same grid barrier with arrival counters: every workgroup adds one to
+// the counter of its group (G = min(8, workgroups) groups, workgroup w in group
+// w % G; counters 64 bytes apart), the last arrival of a group adds one to the
+// top counter, and one thread per workgroup polls the top counter until every
+// group has arrived (epoch x G). Counters only grow within a launch (they are
+// cleared before it), so epoch e is complete when the top counter reaches e G.
+// Bounded like grid_barrier: a poller that gives up sets the timeout word.
+__device__ __forceinline__ bool grid_barrier_ctr(uint32_t *ctrs, uint32_t *timeout, uint32_t epoch, uint32_t limit) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __syncthreads();
+    const uint32_t W = gridDim.x, G = W < 8u ? W : 8u, g = blockIdx.x % G;
+    const uint32_t gsize = W / G + (g < W % G ? 1u : 0u);
+    int ok = 1;
+    if (threadIdx.x == 0) {
+        uint32_t *top = ctrs + 16u * 8u;
+        const uint32_t old = __hip_atomic_fetch_add(ctrs + 16u * g, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (old + 1u == epoch * gsize) __hip_atomic_fetch_add(top, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        uint32_t polls = 0;
+        while (__hip_atomic_load(top, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < epoch * G) {
+            if (__hip_atomic_load(timeout, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u || ++polls > limit) {
+                __hip_atomic_store(timeout, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                ok = 0;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+        }
+    }
+    ok = __syncthreads_and(ok);
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    return ok != 0;
+}
+
 struct PersistArgs {
     double2 *y;         // state (FP64), updated in place
     double2 *w0, *w1;   // FP64 stage vectors
@@ -751,7 +783,7 @@ struct PersistArgs {
 // for each of the four stages, and meets the grid at a barrier after each
 // stage. A workgroup that owns a single tile keeps its metadata in LDS for the
 // whole launch.
-template <int M, int PREC>
+template <int M, int PREC, int BAR>
 __global__ __launch_bounds__(MAX_TILE) void persistent_kernel(Dev D, PersistArgs pa) {
     extern __shared__ __align__(16) unsigned char smem[];
     const InstParams &P = *D.ip;
@@ -808,7 +840,9 @@ __global__ __launch_bounds__(MAX_TILE) void persistent_kernel(Dev D, PersistArgs
                 }
             }
             epoch += 1;
-            if (!grid_barrier(pa.flags, pa.timeout, epoch, pa.limit)) return;
+            if (!(BAR ? grid_barrier_ctr(pa.flags, pa.timeout, epoch, pa.limit)
+                      : grid_barrier(pa.flags, pa.timeout, epoch, pa.limit)))
+                return;
         }
     }
 }
@@ -1193,7 +1227,7 @@ int launch_transpose(const HostTables &t, hipStream_t s, const V *y, V *yT) {
 
 template <int M, int PREC>
 int launch_persistent_m(const HostTables &t, hipStream_t s, PersistArgs pa, bool *used) {
-    auto kern = persistent_kernel<M, PREC>;
+    auto kern = t.tune.persistent == 3 ? persistent_kernel<M, PREC, 1> : persistent_kernel<M, PREC, 0>;
     int dev = 0, ncu = 0, per_cu = 0;
     HIP_TRY(hipGetDevice(&dev));
     HIP_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
@@ -1202,8 +1236,9 @@ int launch_persistent_m(const HostTables &t, hipStream_t s, PersistArgs pa, bool
     uint64_t nwg = std::min<uint64_t>((uint64_t)per_cu * (uint64_t)ncu, t.tiles.size());
     nwg = std::min<uint64_t>(nwg, MAX_PERSIST_WG);
     if (t.tune.max_workgroups > 0) nwg = std::min<uint64_t>(nwg, (uint64_t)t.tune.max_workgroups);
-    // barrier epochs (4 per step) must not wrap within one launch
-    const int64_t chunk = (int64_t)1 << 28;
+    // barrier epochs (4 per step) and the arrival counters (epoch x group
+    // size, at most 256) must not wrap within one launch
+    const int64_t chunk = (int64_t)1 << 22;
     const int64_t total = pa.nsteps;
     Dev D = dev_view(t);
     for (int64_t done = 0; done < total; done += chunk) {
@@ -1522,7 +1557,8 @@ int propagate_impl(const heom_tables *h, void *y_dev, void *work_dev, size_t wor
     }
     hipLaunchKernelGGL(zero_u32_kernel, dim3(64), dim3(256), 0, s, pa.timeout - 1, (uint32_t)(CTRL_BYTES / 4));
     HIP_TRY(hipGetLastError());
-    const bool persist = t.tune.persistent == 1 || (t.tune.persistent == 2 && t.tiles.size() <= 256);
+    const bool persist = t.tune.persistent == 1 || t.tune.persistent == 3 ||
+                         (t.tune.persistent == 2 && t.tiles.size() <= 256);
     bool used = false;
     if (persist)
         if (int rc = launch_persistent(t, s, pa, precision, &used)) return rc;
@@ -1797,7 +1833,7 @@ int heom_propagate_noalloc(const heom_tables *h, void *y_dev, double dt, int64_t
 int heom_set_tuning(heom_tables *h, const heom_tuning *tu) {
     if (!h || !tu) return fail(HEOM_E_INVAL, "NULL argument");
     HostTables &t = h->t;
-    if (tu->persistent < 0 || tu->persistent > 2) return fail(HEOM_E_INVAL, "persistent must be 0, 1 or 2");
+    if (tu->persistent < 0 || tu->persistent > 3) return fail(HEOM_E_INVAL, "persistent must be 0, 1, 2 or 3");
     if (tu->cache_policy < 0 || tu->cache_policy > 7) return fail(HEOM_E_INVAL, "cache_policy must be 0..7");
     if (tu->transposed < -1 || tu->transposed > 1) return fail(HEOM_E_INVAL, "transposed must be -1, 0 or 1");
     if (tu->compact < 0 || tu->compact > 1) return fail(HEOM_E_INVAL, "compact must be 0 or 1");

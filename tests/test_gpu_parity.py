@@ -251,14 +251,18 @@ def test_propagate_zero_steps_and_determinism():
     assert np.array_equal(a, b) and np.array_equal(oa, ob)
 
 
+@pytest.mark.parametrize("mode", [1, 3])
 @pytest.mark.parametrize("precision", [0, 1])
-def test_persistent_equals_stage_launches(precision):
+def test_persistent_equals_stage_launches(precision, mode):
+    """The persistent kernel (one cooperative launch, grid barriers between
+    stages: every workgroup polls every flag (mode 1) or arrival counters
+    (mode 3)) gives bitwise the stage launches' results."""
     for name, steps in (("localized", 200), ("saturated", 30)):
         p = W.WORKLOADS[name]()
         T, torch = upload(p)
         state = "site1" if name == "localized" else "upper_polariton"
         t0 = named_tier0(T, p, state)
-        T.set_tuning(persistent=1)
+        T.set_tuning(persistent=mode)
         a, oa = gpu_propagate(T, torch, t0, 0.02, steps, 10, precision)
         T.set_tuning(persistent=0)
         b, ob = gpu_propagate(T, torch, t0, 0.02, steps, 10, precision)
@@ -303,23 +307,26 @@ def test_split_top_tier_launch_identical():
 
 
 def test_persistent_few_workgroups_many_tiles():
-    # workgroups that own several tiles each restage metadata per tile
+    # workgroups that own several tiles each restage metadata per tile; 37
+    # workgroups in 8 barrier groups of unequal size (mode 3)
     p = W.config_saturated()
     T, torch = upload(p)
     t0 = named_tier0(T, p, "upper_polariton")
     T.set_tuning(persistent=0)
     ref, oref = gpu_propagate(T, torch, t0, 0.02, 20, 5)
-    T.set_tuning(persistent=1, max_workgroups=37)
-    y, o = gpu_propagate(T, torch, t0, 0.02, 20, 5)
-    assert np.array_equal(y, ref) and np.array_equal(o, oref)
+    for mode in (1, 3):
+        T.set_tuning(persistent=mode, max_workgroups=37)
+        y, o = gpu_propagate(T, torch, t0, 0.02, 20, 5)
+        assert np.array_equal(y, ref) and np.array_equal(o, oref), mode
 
 
-def test_barrier_timeout_is_reported():
+@pytest.mark.parametrize("mode", [1, 3])
+def test_barrier_timeout_is_reported(mode):
     from paper_2608_20657_amd import heom
     p = W.config_localized()
     T, torch = upload(p)
     t0 = named_tier0(T, p, "site1")
-    T.set_tuning(persistent=1, spin_limit=1)      # barriers give up almost at once
+    T.set_tuning(persistent=mode, spin_limit=1)   # barriers give up almost at once
     with pytest.raises(heom.HeomError) as e:
         gpu_propagate(T, torch, t0, 0.02, 50, 10)
     assert e.value.code == -8
