@@ -168,10 +168,12 @@ __device__ __forceinline__ double2 cscale(double s, double2 a) { return make_dou
 __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
     return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
-// acc += w * v
+// acc += w * v, as explicit fused multiply-adds: their rounding is fixed,
+// so kernel variants that order or contract the surrounding code differently
+// (the top-tier variant, batch kernels) still sum a variable's terms alike
 __device__ __forceinline__ void cfma(double2 &acc, double2 w, double2 v) {
-    acc.x += w.x * v.x - w.y * v.y;
-    acc.y += w.x * v.y + w.y * v.x;
+    acc.x = fma(-w.y, v.y, fma(w.x, v.x, acc.x));
+    acc.y = fma(w.y, v.x, fma(w.x, v.y, acc.y));
 }
 
 // blockIdx -> tile such that each of the 8 XCDs (workgroups are dealt to
@@ -393,8 +395,9 @@ __device__ __forceinline__ double2 load_own(const StageArgs &a, uint32_t j) {
 //    channel k, the row molecule raised (k), lowered (M+k), the column
 //    molecule raised (2M+k), lowered (3M+k) (Eqs. uvar-up, uvar-down). The
 //    record names the live slots and where their target indices sit in the
-//    tile's list; the gathers are issued together and their weighted sum is
-//    formed before the barrier that publishes the tile's values.
+//    tile's list; the gathers go out in one batch (two, up moves then down
+//    moves, where m >= 3 and the tier has up moves) and their weighted sum
+//    is formed before the barrier that publishes the tile's values.
 // 3. Grouped sums (Eqs. grouped-row-sum, grouped-column-sum, HZ): in each
 //    block, the thread at position l < 2G+1 forms one of them -- l = 0 the
 //    Z bracket sum_q M_q (X_q - Y_q), l = 1..G the row sum R_{l-1}, l =
@@ -483,21 +486,13 @@ __device__ __forceinline__ void process_tile(const InstParams &P, const Dev &D, 
     double2 hier = make_double2(0.0, 0.0);
     if (active) {
         const CatRec cq = A > 0 ? cats[A - 1] : CatRec{}, cr2 = B > 0 ? cats[B - 1] : CatRec{};
-        uint32_t idx[4 * M];
-        double2 v[4 * M];   // FP64 gathers
-        float2 f[4 * M];    // FP32 gathers, widened where they are used
-#pragma unroll
-        for (int j = 0; j < 4 * M; ++j) {
-            const bool up_slot = ((j / M) & 1) == 0;   // slots 0..M-1 and 2M..3M-1 are up moves
-            idx[j] = (!(TOP && up_slot) && ((live >> j) & 1u)) ? S.gix[goff + __popc(live & ((1u << j) - 1u))] : 0u;
-        }
         // Column-move gathers (slots 2M..4M-1) read the transposed copy when
         // there is one. With policy bit 3 the ADOs are Hermitian
         // (rho_n^dagger = rho_n): the entry with row and column exchanged,
         // read from `in` itself at the position the transposed copy would
         // have, is the complex conjugate of the one needed; it is conjugated
         // where it is used. Nothing is done to a value between its load and
-        // its use, so the loads of all slots go out as one batch.
+        // its use, so the loads of a phase go out as one batch.
         const bool mirror = (a.policy & 8u) != 0;
         const double2 *c64 = (mirror || !a.inT64) ? a.in64 : a.inT64;
         const float2 *c32 = (mirror || !a.inT32) ? a.in32 : a.inT32;
@@ -505,27 +500,6 @@ __device__ __forceinline__ void process_tile(const InstParams &P, const Dev &D, 
         // with a constant for the dead slots it moves each widening into the
         // load's branch, which then waits for that load alone
         const float fz = __int_as_float((int)(a.policy >> 16));
-#pragma unroll
-        for (int j = 0; j < 4 * M; ++j) {
-            const bool up_slot = ((j / M) & 1) == 0;
-            const bool colmv = j >= 2 * M;
-            v[j] = make_double2(0.0, 0.0);
-            f[j] = make_float2(fz, fz);
-            if (!(TOP && up_slot) && ((live >> j) & 1u)) {
-                if (HAS64) v[j] = (colmv ? c64 : a.in64)[idx[j]];
-                if (HAS32) f[j] = (colmv ? c32 : a.in32)[idx[j]];
-            }
-        }
-        auto gv = [&](int j) -> double2 {
-            double2 r = v[j];
-            if (HAS32) {
-                r.x += (double)f[j].x;
-                r.y += (double)f[j].y;
-            }
-            return r;
-        };
-        S.val[vt] = own;
-        if (has_mirror) S.val[vmir] = make_double2(own.x, -own.y);
         // row moves -i sqrt((n+1)|c|), -i sqrt(n/|c|) c_k (P: c_k - cc_k);
         // column moves +i sqrt((n+1)|c|), +i sqrt(n/|c|) cc_k
         const int L1 = P.L + 1;
@@ -537,16 +511,73 @@ __device__ __forceinline__ void process_tile(const InstParams &P, const Dev &D, 
             const uint64_t b = (uint64_t)__double_as_longlong(w.y) ^ ((uint64_t)csign << 32);
             return make_double2(w.x, __longlong_as_double((long long)b));
         };
+        // The terms are summed in one fixed order of positions: row up moves
+        // (slot k), column up moves (2M+k), row down moves (M+k), column down
+        // moves (3M+k). With m >= 3 and up moves present the gathers go out
+        // in two phases, the up moves and then the down moves: all 4M slots
+        // in flight at once held 104-109 VGPRs at m = 4 (4 waves per SIMD).
+        // The top tier has no up moves and skips their positions.
+        constexpr int P0 = TOP ? 2 * M : 0;
+        constexpr int NPH = (!TOP && M >= 3) ? 2 : 1;
+        constexpr int SPP = (4 * M - P0) / NPH;
+        auto slot_at = [](int q) { return q < M ? q : (q < 2 * M ? q + M : (q < 3 * M ? q - M : q)); };
+        uint32_t gph = goff;
 #pragma unroll
-        for (int k = 0; k < M; ++k) {
-            const uint32_t nq = vbyte(cq.vec, k), nr = vbyte(cr2.vec, k);
-            const double dq = dn[k * L1 + nq], dr = dn[k * L1 + nr];
-            const double cre = kind == KIND_P ? P.cr[k] - P.ccr[k] : P.cr[k];
-            const double cim = kind == KIND_P ? P.ci[k] - P.cci[k] : P.ci[k];
-            if (!TOP) cfma(hier, make_double2(0.0, -up[k * L1 + nq]), gv(k));
-            cfma(hier, make_double2(dq * cim, -dq * cre), gv(M + k));
-            if (!TOP) cfma(hier, make_double2(0.0, up[k * L1 + nr]), conj_if(gv(2 * M + k)));
-            cfma(hier, make_double2(-dr * P.cci[k], dr * P.ccr[k]), conj_if(gv(3 * M + k)));
+        for (int ph = 0; ph < NPH; ++ph) {
+            uint32_t idx[SPP];
+            double2 v[SPP];   // FP64 gathers
+            float2 f[SPP];    // FP32 gathers, widened where they are used
+#pragma unroll
+            for (int i = 0; i < SPP; ++i) {
+                const int j = slot_at(P0 + ph * SPP + i);
+                idx[i] = ((live >> j) & 1u) ? S.gix[gph + __popc(live & ((1u << j) - 1u))] : 0u;
+            }
+#pragma unroll
+            for (int i = 0; i < SPP; ++i) {
+                const int j = slot_at(P0 + ph * SPP + i);
+                const bool colmv = j >= 2 * M;
+                v[i] = make_double2(0.0, 0.0);
+                f[i] = make_float2(fz, fz);
+                if ((live >> j) & 1u) {
+                    if (HAS64) v[i] = (colmv ? c64 : a.in64)[idx[i]];
+                    if (HAS32) f[i] = (colmv ? c32 : a.in32)[idx[i]];
+                }
+            }
+            if (ph == 0) {
+                S.val[vt] = own;
+                if (has_mirror) S.val[vmir] = make_double2(own.x, -own.y);
+            }
+#pragma unroll
+            for (int i = 0; i < SPP; ++i) {
+                const int j = slot_at(P0 + ph * SPP + i);
+                const int k = j % M, grp = j / M;   // 0 row up, 1 row down, 2 column up, 3 column down
+                double2 z = v[i];
+                if (HAS32) {
+                    z.x += (double)f[i].x;
+                    z.y += (double)f[i].y;
+                }
+                double2 w;
+                if (grp == 0) {
+                    w = make_double2(0.0, -up[k * L1 + vbyte(cq.vec, k)]);
+                } else if (grp == 1) {
+                    const double dq = dn[k * L1 + vbyte(cq.vec, k)];
+                    const double cre = kind == KIND_P ? P.cr[k] - P.ccr[k] : P.cr[k];
+                    const double cim = kind == KIND_P ? P.ci[k] - P.cci[k] : P.ci[k];
+                    w = make_double2(dq * cim, -dq * cre);
+                } else if (grp == 2) {
+                    w = make_double2(0.0, up[k * L1 + vbyte(cr2.vec, k)]);
+                    z = conj_if(z);
+                } else {
+                    const double dr = dn[k * L1 + vbyte(cr2.vec, k)];
+                    w = make_double2(-dr * P.cci[k], dr * P.ccr[k]);
+                    z = conj_if(z);
+                }
+                cfma(hier, w, z);
+            }
+            // the down moves' index reads (and so their loads) depend on the
+            // up moves' sum: the compiler would otherwise hoist them and hold
+            // all slots at once
+            if (NPH == 2 && ph == 0) asm("" : "+v"(gph) : "v"(hier.x), "v"(hier.y));
         }
     }
     double *md = S.md + (H.cat_base - TR.c0);
