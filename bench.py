@@ -106,6 +106,17 @@ def run_solve(T, torch, tier0, dt, steps, obs_every, precision):
     return y, work, obs, s
 
 
+def element_bytes_per_step(info):
+    """FP64 bytes of one RK4 step counted by element: every stage reads the
+    input at the distinct positions it reads (own values and gather
+    targets), stages 2-4 also the base term at the own entries, every stage
+    writes the whole output, plus four stages of table reads. Compact tiles
+    read fewer elements than the method-level count assumes; HBM moves
+    128-byte lines, and those lines cover nearly the whole state."""
+    return (16 * (4 * info["read_entries"] + 3 * info["own_entries"] + 4 * info["n_var"])
+            + 4 * info["stage_table_bytes"])
+
+
 def time_propagate(T, torch, tier0, dt, steps, warmup, obs_every, precision):
     """Warm up, then time `steps` RK4 steps from rho(0) with HIP events on the
     launch stream (and wall clock, both bracketed by device syncs)."""
@@ -266,6 +277,7 @@ def batched_section(torch, steps, warmup, n=512, seed=0, dt=0.02, flag=0, compac
     # tables every stage reads: each instance's tiles read its structure's
     # metadata (shared images are re-read per instance)
     tab = sum(x[1].info()["stage_table_bytes"] for x in inst)
+    elem = sum(element_bytes_per_step(x[1].info()) for x in inst)
     batch = heom.Batch(len(inst))
     obs_bufs = []
     for i, (q, T, params, y, work, t0v, _) in enumerate(inst):
@@ -286,6 +298,7 @@ def batched_section(torch, steps, warmup, n=512, seed=0, dt=0.02, flag=0, compac
            "median_instance_vars": int(sorted(x[6] for x in inst)[len(inst) // 2]),
            "steps": steps, "warmup": warmup, "table_build_s": round(build_s, 2), "hermitian_ados": bool(flag),
            "table_bytes_read_per_stage": tab,
+           "element_bytes_per_step": elem,
            "tuned_tile_vars": tiles or None,
            "tuned_launch_shape": ({"best": shape["best"], "ms_per_step": {f"merge={c['merge_tiles']},share="
                                    f"{c['share_slots']}": round(t, 3) for c, t in shape["results"]}}
@@ -494,6 +507,7 @@ def probe_section(torch, args, herm, general=True):
     launch_ms = rms / (4 * args.roofline_steps)
     bytes_launch = ri["n_var"] * stage_bytes_per_var(0) / 4.0 + ri["stage_table_bytes"]
     achieved = bytes_launch / (launch_ms * 1e-3) / 1e9
+    elem_launch = element_bytes_per_step(ri) / 4.0
     traffic = load_traffic(PROFILE_TRAFFIC)
     out = {
         "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -507,6 +521,8 @@ def probe_section(torch, args, herm, general=True):
                     "278 MB per FP64 vector)",
         "algorithmic_bytes_per_launch": int(bytes_launch),
         "bytes_per_var": stage_bytes_per_var(0) / 4.0, "table_bytes_read": ri["stage_table_bytes"],
+        "element_bytes_per_launch": int(elem_launch),
+        "frac_element_bytes": round(elem_launch / (launch_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
         "mean_launch_us": round(launch_ms * 1e3, 2),
         "rhs_updates_per_s": ri["n_var"] * 4 * args.roofline_steps / (rms / 1e3),
         "table_build_s": round(build_s, 2),
@@ -653,6 +669,9 @@ def main():
             "mean_launch_us": round(f64["ms_per_step"] * 1e3, 1),
             "copy_GBps": copy_gbs,
             "frac_of_copy": round(f64["algorithmic_GBps"] / copy_gbs, 4),
+            "element_bytes_per_launch": bt["element_bytes_per_step"],
+            "frac_element_bytes": round(bt["element_bytes_per_step"] / (f64["ms_per_step"] * 1e-3) / 1e9
+                                        / HBM_PEAK_GBS, 4),
         },
         "batched": bt,
     }

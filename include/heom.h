@@ -99,6 +99,11 @@ typedef struct heom_sizes {
     int32_t compact;         /* 1 if the tiles are compact (see heom_tuning) */
     int64_t stage_table_bytes; /* bytes of the table image one stage reads (compact tiles leave the
                                   record slots of their mirrored entries unread) */
+    int64_t own_entries;     /* state entries one right-hand side loads as threads' own values
+                                (n_var; compact tiles: the covered entries) */
+    int64_t read_entries;    /* distinct state positions one right-hand side reads: own values and
+                                hierarchy gather targets (element level; at 128-byte line level a
+                                compact RHS still touches nearly every line of the state) */
 } heom_sizes;
 
 /* Build the pattern list, unique-variable layout and connection tables of

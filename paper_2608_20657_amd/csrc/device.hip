@@ -272,9 +272,14 @@ struct StageArgs {
 
 enum { BASE_NONE = 0, BASE_IN = 1, BASE_Y = 2 };
 
-// LDS carve-up of one workgroup: tile values and grouped sums, pattern headers,
-// categories, coefficient tables, category multiplicities, gather indices (last,
-// so that a launch whose tiles have shorter lists can allocate less).
+// LDS carve-up of one workgroup: tile values, pattern headers, categories,
+// coefficient tables, category multiplicities, gather indices, grouped sums.
+// The gather indices are read only before the workgroup's first barrier and
+// the grouped sums written only after it, so a workgroup that stages its
+// tile's metadata for one stage (`overlay`) keeps the sums in the gather
+// list's place: its LDS is the larger of the two, not their sum (the
+// lower-tier tiles of the probe: 25.1 -> 18.0 KB). The persistent kernel
+// keeps a tile's metadata for every stage, and so the sums after the list.
 struct Smem {
     double2 *val;
     double2 *rc;      // grouped sums of the tile's blocks (see process_tile)
@@ -283,17 +288,19 @@ struct Smem {
     uint32_t *gix;
     double *lut;
     double *md;       // M_q of the tile's categories as doubles (M_0 resolved per instance)
+    uint32_t rco;     // rc - val, in values
 };
 
-__device__ __forceinline__ Smem carve(unsigned char *smem, const InstParams &P) {
+__device__ __forceinline__ Smem carve(unsigned char *smem, const InstParams &P, bool overlay) {
     Smem S;
     S.val = reinterpret_cast<double2 *>(smem);
-    S.rc = S.val + P.val_len;
-    S.hdr = reinterpret_cast<PatHdr *>(smem + 32u * P.val_len);
+    S.hdr = reinterpret_cast<PatHdr *>(smem + 16u * P.val_len);
     S.cat = reinterpret_cast<CatRec *>(S.hdr + P.max_np);
     S.lut = reinterpret_cast<double *>(S.cat + P.max_nc);
     S.md = S.lut + 2u * (uint32_t)P.m * (uint32_t)(P.L + 1);
     S.gix = reinterpret_cast<uint32_t *>(S.md + ((P.max_nc + 1u) & ~1u));
+    S.rc = reinterpret_cast<double2 *>(S.gix + (overlay ? 0u : (P.max_ng + 3u) & ~3u));
+    S.rco = (uint32_t)(S.rc - S.val);
     return S;
 }
 
@@ -314,6 +321,7 @@ __device__ __forceinline__ Smem carve_pair(unsigned char *smem, const InstParams
     unsigned char *h = smem + pair_shared_bytes(P) + half * pair_half_bytes(P);
     S.val = reinterpret_cast<double2 *>(h);
     S.rc = S.val + P.val_len;
+    S.rco = P.val_len;
     S.lut = reinterpret_cast<double *>(h + 32u * P.val_len);
     S.md = S.lut + 2u * (uint32_t)P.m * (uint32_t)(P.L + 1);
     return S;
@@ -623,8 +631,8 @@ __device__ __forceinline__ void process_tile(const InstParams &P, const Dev &D, 
         //   Z: sum_q M_q (X_q - Y_q)   X_q: Z - R_q   Y_r: C_r - Z
         //   P_q: Y_q - X_q             S_qr, T_q: Y_r - X_q
         // (compact tiles: C_r = conj(R_r))
-        const double2 *VR = S.val;   // S.rc follows S.val: index val_len + i is rc[i]
-        const uint32_t vl = P.val_len;
+        const double2 *VR = S.val;   // index rco + i is rc[i]
+        const uint32_t vl = S.rco;
         uint32_t i1, i2;
         if (kind == KIND_Z) { i1 = vl + base; i2 = base; }
         else if (kind == KIND_X) { i1 = base; i2 = vl + base + A; }
@@ -718,7 +726,7 @@ template <int M, bool HAS64, bool HAS32, int BASE, bool EXTRA, bool OUT64, bool 
 __global__ __launch_bounds__(MAX_TILE) void stage_kernel(Dev D, StageArgs a, int xcd) {
     extern __shared__ __align__(16) unsigned char smem[];
     const InstParams &P = *D.ip;
-    const Smem S = carve(smem, P);
+    const Smem S = carve(smem, P, true);
     const uint32_t tile = a.tile0 + (xcd ? xcd_tile(blockIdx.x, gridDim.x) : blockIdx.x);
     const TileRec TR = D.tiles[tile];
     process_tile<M, HAS64, HAS32, BASE, EXTRA, OUT64, TOP, CM>(P, D, TR, S, a, tile == 0, true, lut_words(P));
@@ -818,7 +826,7 @@ template <int M, int PREC, int BAR>
 __global__ __launch_bounds__(MAX_TILE) void persistent_kernel(Dev D, PersistArgs pa) {
     extern __shared__ __align__(16) unsigned char smem[];
     const InstParams &P = *D.ip;
-    const Smem S = carve(smem, P);
+    const Smem S = carve(smem, P, false);
     const uint32_t T = P.n_tiles, W = gridDim.x, w = blockIdx.x;
     // tiles of this workgroup: XCD x = w % 8 owns tiles [x*T/8, (x+1)*T/8)
     const uint32_t X = W < 8 ? W : 8;
@@ -986,7 +994,7 @@ __device__ __forceinline__ BatchCtx batch_ctx(const SlotRec &rec, uint32_t tile,
 template <int M, int PREC, bool TOP, int SV>
 __device__ __forceinline__ void batch_tile(const BatchCtx &c, unsigned char *smem, int stage = STAGE_ALL) {
     const InstParams &P = *c.D.ip;
-    const Smem S = carve(smem, P);
+    const Smem S = carve(smem, P, true);
     const uint32_t lw = lut_words(P);
     if (PREC == HEOM_FP64) {
         if (SV == 0) process_tile<M, true, false, BASE_IN, false, true, TOP, 2>(P, c.D, c.TR, S, c.a, c.first, stage, lw);
@@ -1262,7 +1270,7 @@ int launch_persistent_m(const HostTables &t, hipStream_t s, PersistArgs pa, bool
     int dev = 0, ncu = 0, per_cu = 0;
     HIP_TRY(hipGetDevice(&dev));
     HIP_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
-    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, t.tile_vars, t.lds_bytes));
+    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, t.tile_vars, t.lds_persist));
     if (per_cu < 1) { *used = false; return HEOM_OK; }
     uint64_t nwg = std::min<uint64_t>((uint64_t)per_cu * (uint64_t)ncu, t.tiles.size());
     nwg = std::min<uint64_t>(nwg, MAX_PERSIST_WG);
@@ -1280,7 +1288,7 @@ int launch_persistent_m(const HostTables &t, hipStream_t s, PersistArgs pa, bool
         HIP_TRY(hipGetLastError());
         void *args[] = {&D, &a};
         HIP_TRY(hipLaunchCooperativeKernel(reinterpret_cast<const void *>(kern), dim3((uint32_t)nwg),
-                                           dim3(t.tile_vars), args, t.lds_bytes, s));
+                                           dim3(t.tile_vars), args, t.lds_persist, s));
     }
     *used = true;
     return HEOM_OK;
@@ -1669,6 +1677,8 @@ int heom_table_info(const heom_tables *h, heom_sizes *out) {
     for (const TileRec &r : t.tiles) covered += r.nv;
     out->stage_table_bytes = (int64_t)t.image.size() -
                              (t.compact ? (int64_t)((sizeof(VarRec) + sizeof(uint16_t)) * (t.n_var - covered)) : 0);
+    out->own_entries = t.own_entries;
+    out->read_entries = t.read_entries;
     return HEOM_OK;
 }
 
@@ -2171,7 +2181,10 @@ int heom_batch_commit(heom_batch *b, void *dev, size_t bytes, void *stream) {
                     if (j1 <= j0) continue;
                     for (uint32_t j = j0; j < j1; ++j) P.tiles.push_back(BatchTile{(uint32_t)i, top ? (j | BTILE_TOP) : j});
                     P.members.push_back(Member{(uint32_t)i, j0, j1});
-                    P.g.lds = std::max<uint32_t>(P.g.lds, t.lds_bytes);
+                    // LDS for the longest gather list among the group's tiles
+                    // (the top tier's lists are about a third as long)
+                    const uint32_t lds = split < T ? (top ? t.lds_top : t.lds_low) : t.lds_bytes;
+                    P.g.lds = std::max<uint32_t>(P.g.lds, lds);
                 }
                 if (!P.tiles.empty()) pend.push_back(std::move(P));
             }

@@ -161,6 +161,9 @@ struct HostTables {
     std::vector<uint16_t> vloc;         // compact tiles: tile-relative variable of each thread
     uint32_t max_np = 0, max_nc = 0, max_ng = 0, lds_bytes = 0, val_len = 0;
     uint32_t lds_low = 0, lds_top = 0;      // LDS of a launch over the tiles below / in the top tier
+    uint32_t lds_persist = 0;               // LDS of the persistent kernel (lists kept for every stage)
+    uint32_t own_entries = 0;           // entries loaded as threads' own values (compact: the covered ones)
+    uint32_t read_entries = 0;          // distinct positions one right-hand side reads (own values, gather targets)
     std::vector<uint16_t> pat_ids;      // flat: d dist ids + pool ids
     std::vector<uint32_t> pat_start;    // per pattern start in pat_ids, then end
     uint32_t n_var = 0;

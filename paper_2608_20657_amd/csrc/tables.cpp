@@ -584,22 +584,50 @@ int make_tiles(HostTables *t, int tile_vars, std::string *err) {
     t->top_tile = (uint32_t)t->tiles.size();
     for (size_t k = 0; k < t->tiles.size(); ++k)
         if (t->hdr[t->tiles[k].p0].tier == t->L) { t->top_tile = (uint32_t)k; break; }
-    // LDS per workgroup: values, grouped sums, pattern headers, categories,
-    // coefficient tables, category multiplicities (FP64, padded to 16 bytes),
-    // then the gather indices. The gather list is last so that a launch over
-    // tiles with shorter lists can allocate less (the top tier's lists, which
-    // have no up moves, are about a third as long).
-    const uint32_t lds_fixed = 32u * t->val_len + 32u * t->max_np + 16u * t->max_nc +
+    // LDS per workgroup: values, pattern headers, categories, coefficient
+    // tables, category multiplicities (FP64, padded to 16 bytes), then the
+    // gather indices and the grouped sums. A workgroup that stages its tile
+    // for one stage keeps the sums in the gather list's place (the list is
+    // dead by then), so it needs the larger of the two; a launch over tiles
+    // with shorter lists can allocate less (the top tier's lists, which have
+    // no up moves, are about a third as long). The persistent kernel keeps
+    // the lists for every stage: the sums follow the longest list.
+    const uint32_t lds_fixed = 16u * t->val_len + 32u * t->max_np + 16u * t->max_nc +
                                16u * (uint32_t)t->m * (uint32_t)(t->L + 1) + 8u * ((t->max_nc + 1u) & ~1u);
+    const uint32_t sums = 16u * t->val_len;
     uint32_t ng_low = 0, ng_top = 0;
     for (size_t k = 0; k < t->tiles.size(); ++k) {
         uint32_t &ng = k < t->top_tile ? ng_low : ng_top;
         ng = std::max(ng, t->tiles[k].ng);
     }
-    t->lds_bytes = lds_fixed + 4u * ((t->max_ng + 3u) & ~3u);
-    t->lds_low = lds_fixed + 4u * ((ng_low + 3u) & ~3u);
-    t->lds_top = lds_fixed + 4u * ((ng_top + 3u) & ~3u);
-    if (t->lds_bytes > 64u * 1024u) {
+    auto list_bytes = [](uint32_t ng) { return 4u * ((ng + 3u) & ~3u); };
+    t->lds_bytes = lds_fixed + std::max(list_bytes(t->max_ng), sums);
+    t->lds_low = lds_fixed + std::max(list_bytes(ng_low), sums);
+    t->lds_top = lds_fixed + std::max(list_bytes(ng_top), sums);
+    t->lds_persist = lds_fixed + list_bytes(t->max_ng) + sums;
+    // element-level reads of one right-hand side: own values and the
+    // distinct gather targets (a transposed copy's positions counted as the
+    // vector's); with compact tiles the own values are the covered entries
+    {
+        std::vector<unsigned char> seen(t->n_var, 0);
+        uint32_t own = 0, rd = 0;
+        for (const TileRec &r : t->tiles) {
+            own += r.nv;
+            for (uint32_t th = 0; th < r.nv; ++th) {
+                const uint32_t v = r.v0 + (t->compact ? t->vloc[r.v0 + th] : th);
+                rd += seen[v] ? 0u : 1u;
+                seen[v] = 1;
+            }
+            for (uint32_t g = 0; g < r.ng; ++g) {
+                const uint32_t v = t->gidx[r.g0 + g];
+                rd += seen[v] ? 0u : 1u;
+                seen[v] = 1;
+            }
+        }
+        t->own_entries = own;
+        t->read_entries = rd;
+    }
+    if (t->lds_persist > 64u * 1024u) {
         *err = "tile needs more than 64 KiB of LDS";
         return HEOM_E_UNSUPPORTED;
     }

@@ -67,7 +67,8 @@ class _Sizes(ctypes.Structure):
                 ("work_bytes_fp32", ctypes.c_int64), ("tier0_size", ctypes.c_int64),
                 ("max_G", ctypes.c_int32), ("tile_vars", ctypes.c_int32), ("hier_gathers", ctypes.c_int64),
                 ("rhs_work_bytes", ctypes.c_int64), ("transposed", ctypes.c_int32), ("compact", ctypes.c_int32),
-                ("stage_table_bytes", ctypes.c_int64)]
+                ("stage_table_bytes", ctypes.c_int64), ("own_entries", ctypes.c_int64),
+                ("read_entries", ctypes.c_int64)]
 
 
 def _load():

@@ -6,6 +6,7 @@
 // move names the mirrored position of the entry a plain table names; every
 // tile's metadata fits the LDS its launch allocates.
 // Prints "ok" and exits 0, or names the first failure and exits 1.
+#include <algorithm>
 #include <cstdio>
 #include <cstdlib>
 #include <string>
@@ -72,15 +73,23 @@ static int check(int64_t N, int m, int L, int d, int tv) {
                 if (plain.gidx[g] >= plain.n_var) return fail("gather index", g, plain.gidx[g]);
             }
         }
-    // LDS: the gather list is the last section of a workgroup's LDS, so a
-    // tile's list must fit what its launch allocates (lower tiers / top tier)
+    // LDS: values, headers, categories, coefficient tables and multiplicities,
+    // then the gather list, whose place the grouped sums (16 bytes per value)
+    // take once the list has been read; a tile's list and the sums must fit
+    // what its launch allocates (lower tiers / top tier), and the persistent
+    // kernel, which keeps the lists, holds both
     for (const HostTables *T : {&plain, &trans, &comp}) {
-        const uint32_t fixed = T->lds_bytes - 4u * ((T->max_ng + 3u) & ~3u);
+        const uint32_t fixed = 16u * T->val_len + 32u * T->max_np + 16u * T->max_nc +
+                               16u * (uint32_t)T->m * (uint32_t)(T->L + 1) + 8u * ((T->max_nc + 1u) & ~1u);
+        const uint32_t sums = 16u * T->val_len;
+        auto list = [](uint32_t ng) { return 4u * ((ng + 3u) & ~3u); };
         if (T->lds_low > T->lds_bytes || T->lds_top > T->lds_bytes) return fail("launch LDS", T->lds_low, T->lds_top);
+        if (T->lds_persist != fixed + list(T->max_ng) + sums) return fail("persistent LDS", T->lds_persist, T->max_ng);
         for (size_t k = 0; k < T->tiles.size(); ++k) {
             const TileRec &R = T->tiles[k];
             const uint32_t alloc = k < T->top_tile ? T->lds_low : T->lds_top;
-            if (R.np > T->max_np || R.nc > T->max_nc || fixed + 4u * ((R.ng + 3u) & ~3u) > alloc)
+            if (R.np > T->max_np || R.nc > T->max_nc || fixed + std::max(list(R.ng), sums) > alloc ||
+                fixed + std::max(list(R.ng), sums) > T->lds_bytes)
                 return fail("tile LDS", (long long)k, R.ng);
         }
     }

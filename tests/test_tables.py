@@ -193,3 +193,20 @@ def test_compact_tiles_sizes_and_knob():
     assert T.info()["compact"] == 0 and T.info()["table_bytes"] == i0["table_bytes"]
     with pytest.raises(heom.HeomError):
         T.set_tuning(compact=2)
+
+
+def test_element_read_counts():
+    """Element-level reads of one right-hand side: plain tiles load every
+    entry as a thread's own value; compact tiles load the entries with row <=
+    column and the T_q (counted here from the oracle's layout), and their
+    gathers at mirrored positions also read entries below the diagonal."""
+    p = W.random_problem(6, 3, 3, 1, seed=4)
+    T = heom.Tables(p)
+    i0 = T.info()
+    assert i0["own_entries"] == i0["n_var"] == i0["read_entries"]
+    T.set_tuning(compact=1)
+    i1 = T.info()
+    S = uvar.UVarSystem(p)
+    covered = sum((b.G + 1) * (b.G + 2) // 2 + b.h for b in S.blocks)
+    assert i1["own_entries"] == covered
+    assert covered < i1["read_entries"] <= i1["n_var"]
