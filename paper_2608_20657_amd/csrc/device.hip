@@ -585,7 +585,7 @@ __device__ __forceinline__ void process_tile(const InstParams &P, const Dev &D, 
             // the down moves' index reads (and so their loads) depend on the
             // up moves' sum: the compiler would otherwise hoist them and hold
             // all slots at once
-            if (NPH == 2 && ph == 0) asm("" : "+v"(gph) : "v"(hier.x), "v"(hier.y));
+            if (ph + 1 < NPH) asm("" : "+v"(gph) : "v"(hier.x), "v"(hier.y));
         }
     }
     double *md = S.md + (H.cat_base - TR.c0);
