@@ -80,6 +80,11 @@ def sha256(path):
     return hashlib.sha256(open(path, "rb").read()).hexdigest()
 
 
+def progress(msg):
+    """One line on stderr per finished section (stdout carries only the JSON line)."""
+    print(f"bench.py: {msg}", file=sys.stderr, flush=True)
+
+
 def load_traffic(path):
     """Counter-derived HBM bytes per launch from a committed profile summary,
     or None once the kernel source has changed since the counters were
@@ -633,6 +638,7 @@ def main():
     bt = batched_section(torch, args.steps, args.warmup, flag=herm, compact=bool(herm), tune_tiles=args.tune_tiles,
                          tune_shape=args.tune_batch)
     f64 = bt["fp64_batched"]
+    progress(f"batched draw done: {f64['ms_per_step']} ms per FP64 step")
     traffic = load_traffic(PROFILE_TRAFFIC_BATCH)
     step_bytes = bt["unique_vars_total"] * stage_bytes_per_var(0) + 4 * bt["table_bytes_read_per_stage"]
     out = {
@@ -680,17 +686,21 @@ def main():
         return
     if not args.no_local:
         out["localized"] = localized_section(torch, args, precision, herm)
+        progress("localized workload done")
     if not args.no_roofline:
         out["roofline_probe"] = probe_section(torch, args, herm)
         out["roofline_probe"]["frac_of_copy"] = round(out["roofline_probe"]["achieved"] / copy_gbs, 4)
+        progress(f"roofline probe done: {out['roofline_probe']['mean_launch_us']} us per stage")
     if not args.no_serve:
         out["serving"] = []
         for spec in [x for x in args.serve_rates.split(",") if x]:
             r, w, d = (float(v) for v in spec.split(":"))
             out["serving"].append(serving_point(torch, r, w, d, precision=serve_prec, flag=herm))
+            progress(f"serving point at {r} req/s done")
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(0.02, args.cpu_var_budget, args.cpu_max_vars, steps=args.cpu_steps)
         out["cpu_baseline"]["speedup_gpu_over_cpu"] = round(out["value"] / out["cpu_baseline"]["value"], 1)
+        progress("CPU baseline done")
 
     print(json.dumps(out), flush=True)
 
