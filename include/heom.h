@@ -164,6 +164,40 @@ int heom_tier0_operator(const heom_tables *t, const double *R, double *out);
  * are 0. */
 int heom_tier0_expand(const heom_tables *t, const double *tier0, double *R);
 
+/* Dense rho_S(t) of one output time by linear reconstruction (Sec. VI.C,
+ * Table II; Eqs. Gt-linearity, Gt-covariance, arbitrary-initial-expansion):
+ * the reduced map is linear in rho_S(0) and covariant under relabelings, so
+ * rho_S(t) is the sum over the five operator types of rho_S(0) of the
+ * representatives' responses, relabeled and weighted by rho_S(0)'s entries
+ * of that type:
+ *   type |c><c|       weight rho0[c][c]         representative d = 0
+ *   type |e_k><c|     weights rho0[k][c]        representative |e_1><c|, d = 1
+ *   type |c><e_k|     weights rho0[c][k]        representative |c><e_1|, d = 1
+ *   type |e_k><e_k|   weights rho0[k][k]        representative |e_1><e_1|, d = 1
+ *   type |e_k><e_l|   weights rho0[k][l], k!=l  representative |e_1><e_2|, d = 2
+ * N: molecules, 1..HEOM_RECON_MAX_N. rho0_dev: device, (N+1)x(N+1) complex
+ * doubles, row-major, index 0 = cavity, 1..N = molecules. R: host, the five
+ * responses at this time as slot matrices (heom_tier0_expand of each
+ * representative's propagated tier-0 block), complex row-major (re, im)
+ * pairs packed in the order above: 3x3, 4x4, 4x4, 4x4, 5x5
+ * (HEOM_RECON_R_DOUBLES doubles); read during the call only. mask: bit t set
+ * = type t (order above) contributes; HEOM_RECON_CE_ADJOINT with bit 2: the
+ * |c><e_1| response is taken as the adjoint of the |e_1><c| one (Eq.
+ * adjoint-preservation; valid when c_check_k = conj(c_k)) and R's third
+ * block is not read. work_dev: device, at least heom_reconstruct_work_bytes(N)
+ * bytes (row and column sums of rho0's molecule block, totals), overwritten.
+ * out_dev: device, (N+1)x(N+1) complex doubles, overwritten; may not alias
+ * rho0_dev or work_dev. Stream-ordered on `stream`, nothing allocated.
+ * Errors: HEOM_E_INVAL (N out of range, NULL pointer, unknown mask bits,
+ * the adjoint flag without bit 2), HEOM_E_TOO_LARGE (work too small). */
+#define HEOM_RECON_MAX_N 4096
+#define HEOM_RECON_R_DOUBLES 164
+#define HEOM_RECON_CE_ADJOINT 32u
+int heom_reconstruct_dense(int64_t N, const void *rho0_dev, const double *R, uint32_t mask, void *work_dev,
+                           size_t work_bytes, void *out_dev, void *stream);
+/* Work bytes heom_reconstruct_dense needs for N molecules (0 if N is out of range). */
+size_t heom_reconstruct_work_bytes(int64_t N);
+
 /* Factorized initial condition (Eqs. factorized-initial-zero/-higher):
  * y_dev (n_var complex128) gets the tier-0 variables `tier0` (host,
  * 2*tier0_size doubles) and zeros elsewhere. Requires heom_upload. */

@@ -40,10 +40,12 @@ def build(verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
     tables_o = os.path.join(BUILD, "tables.o")
     device_o = os.path.join(BUILD, "device.o")
+    recon_o = os.path.join(BUILD, "reconstruct.o")
     _run(["g++"] + HOST_FLAGS + ["-c", os.path.join(CSRC, "tables.cpp"), "-o", tables_o], verbose)
     _run([HIPCC] + HIP_FLAGS + ["-c", os.path.join(CSRC, "device.hip"), "-o", device_o], verbose)
+    _run([HIPCC] + HIP_FLAGS + ["-c", os.path.join(CSRC, "reconstruct.hip"), "-o", recon_o], verbose)
     tmp = LIB + ".tmp"
-    _run([HIPCC, "--offload-arch=" + ARCH, "-shared", "-fPIC", tables_o, device_o, "-o", tmp], verbose)
+    _run([HIPCC, "--offload-arch=" + ARCH, "-shared", "-fPIC", tables_o, device_o, recon_o, "-o", tmp], verbose)
     os.replace(tmp, LIB)
     return LIB
 

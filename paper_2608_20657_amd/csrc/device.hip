@@ -130,6 +130,12 @@ int fail(int code, const std::string &msg) {
     return code;
 }
 
+}  // namespace
+
+int heom::set_error(int code, const std::string &msg) { return fail(code, msg); }
+
+namespace {
+
 #define HIP_TRY(expr)                                                                       \
     do {                                                                                    \
         hipError_t e_ = (expr);                                                             \

@@ -185,6 +185,9 @@ struct HostTables {
 // States of at least this many variables keep transposed copies by default.
 constexpr uint32_t TRANSPOSED_MIN_VARS = 1u << 19;
 
+// Sets the calling thread's error message (heom_last_error) and returns code.
+int set_error(int code, const std::string &msg);
+
 // host-side helpers implemented in tables.cpp
 int build(const heom_problem *p, HostTables *t, std::string *err);
 int set_params(HostTables *t, const heom_problem *p, std::string *err);

@@ -23,6 +23,9 @@ HEOM_FP64 = 0
 HEOM_FP32 = 1
 HEOM_HERMITIAN = 2      # flag OR-ed into precision: every ADO is Hermitian
 HEOM_NOALLOC_WORK_BYTES = 64 << 20   # work memory of heom_propagate_noalloc
+HEOM_RECON_MAX_N = 4096              # molecules of heom_reconstruct_dense's dense output
+HEOM_RECON_R_DOUBLES = 164           # doubles of its five packed slot matrices
+HEOM_RECON_CE_ADJOINT = 32           # mask flag: |c><e_1| response = adjoint of the |e_1><c| one
 ERRORS = {-1: "E_INVAL", -2: "E_NOMEM", -3: "E_TOO_LARGE", -4: "E_HIP", -5: "E_NONFINITE",
           -6: "E_UNSUPPORTED", -7: "E_STATE", -8: "E_TIMEOUT"}
 
@@ -36,7 +39,7 @@ SYMBOLS = ["heom_build_tables", "heom_set_params", "heom_table_info", "heom_uplo
            "heom_upload_params", "heom_batch_create", "heom_batch_set_slot", "heom_batch_clear_slot",
            "heom_batch_device_bytes", "heom_batch_commit", "heom_batch_propagate", "heom_batch_slot_steps",
            "heom_batch_set_graph", "heom_batch_set_merge", "heom_batch_set_share", "heom_batch_status",
-           "heom_batch_free"]
+           "heom_batch_free", "heom_reconstruct_dense", "heom_reconstruct_work_bytes"]
 
 
 class HeomError(RuntimeError):
@@ -113,6 +116,7 @@ def _load():
         "heom_batch_set_merge": [vp, ctypes.c_int32],
         "heom_batch_status": [vp, ctypes.POINTER(ctypes.c_int32), ctypes.c_int32, vp],
         "heom_batch_set_share": [vp, ctypes.c_int32],
+        "heom_reconstruct_dense": [i64, vp, dp, ctypes.c_uint32, vp, ctypes.c_size_t, vp, vp],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -122,6 +126,8 @@ def _load():
     lib.heom_free_tables.restype = None
     lib.heom_batch_free.argtypes = [vp]
     lib.heom_batch_free.restype = None
+    lib.heom_reconstruct_work_bytes.argtypes = [i64]
+    lib.heom_reconstruct_work_bytes.restype = ctypes.c_size_t
     lib.heom_last_error.restype = ctypes.c_char_p
     lib.heom_version.restype = ctypes.c_char_p
     return lib
@@ -420,6 +426,22 @@ class Batch:
         n = ctypes.c_int64()
         _check(LIB.heom_batch_slot_steps(self._h, int(slot), ctypes.byref(n)))
         return n.value
+
+
+def reconstruct_work_bytes(N: int) -> int:
+    return int(LIB.heom_reconstruct_work_bytes(int(N)))
+
+
+def reconstruct_dense(N: int, rho0, R: np.ndarray, mask: int, work, out, stream=None):
+    """heom_reconstruct_dense: rho0 and out device tensors of (N+1)^2
+    complex128, R the HEOM_RECON_R_DOUBLES doubles of the five packed slot
+    matrices (host), work a device buffer of reconstruct_work_bytes(N)."""
+    R = np.ascontiguousarray(R, dtype=np.float64)
+    if R.size != HEOM_RECON_R_DOUBLES:
+        raise ValueError(f"R must hold {HEOM_RECON_R_DOUBLES} doubles")
+    wbytes = work.numel() * work.element_size()
+    _check(LIB.heom_reconstruct_dense(int(N), _ptr(rho0), R.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                      int(mask), _ptr(work), wbytes, _ptr(out), _stream(stream)))
 
 
 def version() -> str:

@@ -18,18 +18,12 @@ suffice. Otherwise the fifth one is run.
 
 Each representative runs on the device through the C ABI (its own tables
 with d distinguished molecules); its tier-0 block at every output time is
-read back and turned into the representative's slot matrix R (cavity,
+read back and turned into the representative's slot matrix (cavity,
 distinguished molecules, two pool molecules; heom_tier0_expand). The dense
-rho_S(t) is then the weighted sum of the relabeled responses, formed in
-closed form per entry: for the d=1 representatives with weights w_i,
-
-    [c,c] = W R_cc     [c,k] = w_k R_c1 + (W - w_k) R_cp     (W = sum_i w_i)
-    [k,k] = w_k R_11 + (W - w_k) R_pp
-    [k,l] = w_k R_1p + w_l R_p1 + (W - w_k - w_l) R_pq          (k != l)
-
-and similarly for the ordered pairs of the d=2 representative. The dense
-output has (N+1)^2 entries per time (the quadratic cost of the requested
-output, not of the propagation).
+rho_S(t) of each output time, the weighted sum of the relabeled responses,
+is formed on the device by heom_reconstruct_dense from rho_S(0) and the
+five slot matrices: one pass over the (N+1)^2 entries, the quadratic cost
+of the requested output, not of the propagation.
 """
 from __future__ import annotations
 
@@ -97,52 +91,22 @@ def gpu_tier0_trajectory(problem, R0: np.ndarray, dt: float, nsteps: int, every:
     return out
 
 
-def _dense_d0(R: np.ndarray, N: int) -> np.ndarray:
-    D = np.empty((N + 1, N + 1), dtype=np.complex128)
-    D[0, 0] = R[0, 0]
-    D[0, 1:] = R[0, 1]
-    D[1:, 0] = R[1, 0]
-    D[1:, 1:] = R[1, 2]
-    idx = np.arange(1, N + 1)
-    D[idx, idx] = R[1, 1]
-    return D
+# packing of the five slot matrices for heom_reconstruct_dense: (name,
+# slots, mask bit), in the order of REPRESENTATIVES
+PACK = [("cc", 3, 1), ("ec", 4, 2), ("ce", 4, 4), ("ee", 4, 8), ("e12", 5, 16)]
 
 
-def _dense_d1(R: np.ndarray, w: np.ndarray) -> np.ndarray:
-    """sum_i w_i U_i G[A] U_i^+ with R the slot matrix of G[A] (slots c, e_1,
-    p, q) and U_i a relabeling taking molecule 1 to i."""
-    N = w.size
-    W = w.sum()
-    D = np.empty((N + 1, N + 1), dtype=np.complex128)
-    D[0, 0] = W * R[0, 0]
-    D[0, 1:] = w * R[0, 1] + (W - w) * R[0, 2]
-    D[1:, 0] = w * R[1, 0] + (W - w) * R[2, 0]
-    D[1:, 1:] = (w[:, None] * R[1, 2] + w[None, :] * R[2, 1]
-                 + (W - w[:, None] - w[None, :]) * R[2, 3])
-    idx = np.arange(1, N + 1)
-    D[idx, idx] = w * R[1, 1] + (W - w) * R[2, 2]
-    return D
-
-
-def _dense_d2(R: np.ndarray, Wm: np.ndarray) -> np.ndarray:
-    """sum_{i != j} Wm_ij U_ij G[A] U_ij^+ with R the slot matrix of G[A]
-    (slots c, e_1, e_2, p, q) and U_ij taking molecules (1, 2) to (i, j)."""
-    N = Wm.shape[0]
-    r, s = Wm.sum(axis=1), Wm.sum(axis=0)
-    W = Wm.sum()
-    rest = W - r - s
-    D = np.empty((N + 1, N + 1), dtype=np.complex128)
-    D[0, 0] = W * R[0, 0]
-    D[0, 1:] = r * R[0, 1] + s * R[0, 2] + rest * R[0, 3]
-    D[1:, 0] = r * R[1, 0] + s * R[2, 0] + rest * R[3, 0]
-    WT = Wm.T
-    D[1:, 1:] = (Wm * R[1, 2] + WT * R[2, 1]
-                 + (r[:, None] - Wm) * R[1, 3] + (s[:, None] - WT) * R[2, 3]
-                 + (r[None, :] - WT) * R[3, 1] + (s[None, :] - Wm) * R[3, 2]
-                 + (W - r[:, None] - s[:, None] - r[None, :] - s[None, :] + Wm + WT) * R[3, 4])
-    idx = np.arange(1, N + 1)
-    D[idx, idx] = r * R[1, 1] + s * R[2, 2] + rest * R[3, 3]
-    return D
+def pack_slots(resp: Dict[str, np.ndarray]) -> np.ndarray:
+    """The responses present in `resp` packed as heom_reconstruct_dense reads
+    them (absent ones as zeros)."""
+    out = []
+    for name, n, _ in PACK:
+        R = resp.get(name)
+        R = np.zeros((n, n), dtype=np.complex128) if R is None else np.asarray(R, dtype=np.complex128)
+        if R.shape != (n, n):
+            raise ValueError(f"slot matrix {name} must be {n}x{n}")
+        out.append(np.ascontiguousarray(R).view(np.float64).ravel())
+    return np.concatenate(out)
 
 
 def plan(problem, rho0: np.ndarray) -> Dict[str, bool]:
@@ -176,6 +140,8 @@ def reconstruct(problem, rho0: np.ndarray, dt: float, nsteps: int, every: int,
         raise ValueError("rho0 must be (N+1)x(N+1)")
     if every < 1 or nsteps % every:
         raise ValueError("nsteps must be a multiple of every")
+    import torch
+    from . import heom
     run = tier0_trajectory or (lambda q, R0, dt_, n_, e_: gpu_tier0_trajectory(q, R0, dt_, n_, e_, precision))
     need = plan(problem, rho0)
     adj = need.pop("ec_for_ce", False)
@@ -185,22 +151,18 @@ def reconstruct(problem, rho0: np.ndarray, dt: float, nsteps: int, every: int,
         if not want or (name == "ce" and adj):
             continue
         traj[name] = run(with_d(problem, d), slot_matrix(d, a, b), dt, nsteps, every)
+    mask = sum(bit for name, _, bit in PACK if need[name])
     if adj and need["ce"]:
-        traj["ce"] = [R.conj().T for R in traj["ec"]]
+        mask |= heom.HEOM_RECON_CE_ADJOINT
     nt = nsteps // every + 1
-    w_ec, w_ce, w_ee = rho0[1:, 0], rho0[0, 1:], np.diag(rho0)[1:]
-    Wm = rho0[1:, 1:] - np.diag(w_ee)
+    s = torch.cuda.current_stream()
+    rho0_dev = torch.from_numpy(np.ascontiguousarray(rho0)).to("cuda")
+    work = torch.empty(heom.reconstruct_work_bytes(N), dtype=torch.uint8, device="cuda")
+    dense = torch.empty((N + 1, N + 1), dtype=torch.complex128, device="cuda")
     out = np.zeros((nt, N + 1, N + 1), dtype=np.complex128)
     for k in range(nt):
-        if need["cc"]:
-            out[k] += rho0[0, 0] * _dense_d0(traj["cc"][k], N)
-        if need["ec"]:
-            out[k] += _dense_d1(traj["ec"][k], w_ec)
-        if need["ce"]:
-            out[k] += _dense_d1(traj["ce"][k], w_ce)
-        if need["ee"]:
-            out[k] += _dense_d1(traj["ee"][k], w_ee)
-        if need["e12"]:
-            out[k] += _dense_d2(traj["e12"][k], Wm)
-    propagated = [n for n in traj if not (n == "ce" and adj)]
+        R = pack_slots({name: tr[k] for name, tr in traj.items()})
+        heom.reconstruct_dense(N, rho0_dev, R, mask, work, dense, s)
+        out[k] = dense.cpu().numpy()
+    propagated = list(traj)
     return {"rho": out, "propagations": propagated, "adjoint_reduction": bool(adj and need["ce"])}
