@@ -464,16 +464,11 @@ __device__ __forceinline__ void process_tile(const InstParams &P, const Dev &D, 
     VarRec vr{0u, 0u};
     if (active) {
         vr = D.vrec[TR.v0 + t];
-        if (cmp) {
-            // the compact index list of the structure image (located from the
-            // header section: a parameter block shares the image's offsets)
-            const uint16_t *vloc = reinterpret_cast<const uint16_t *>(
-                reinterpret_cast<const unsigned char *>(D.hdr) + (P.off_vloc - P.off_hdr));
-            vt = vloc[TR.v0 + t];
+        if (!cmp) {
+            own = load_own<HAS64, HAS32>(a, TR.v0 + vt);
+            if (BASE == BASE_Y) ybv = (a.policy & 2u) ? ld_stream(a.ybase + TR.v0 + vt) : a.ybase[TR.v0 + vt];
+            if (EXTRA) ex = a.extra[TR.v0 + vt];
         }
-        own = load_own<HAS64, HAS32>(a, TR.v0 + vt);
-        if (BASE == BASE_Y) ybv = (a.policy & 2u) ? ld_stream(a.ybase + TR.v0 + vt) : a.ybase[TR.v0 + vt];
-        if (EXTRA) ex = a.extra[TR.v0 + vt];
     }
     if (stage == STAGE_ALL) stage_tile(D, TR, S, lut_w);
     else if (stage == STAGE_LUT) stage_lut_words(D, S, lut_w);
@@ -489,8 +484,18 @@ __device__ __forceinline__ void process_tile(const InstParams &P, const Dev &D, 
     const bool isT = (vr.x >> 17) & 1u;
     const uint32_t goff = vr.x >> 18, live = vr.y;
     const PatHdr H = S.hdr[p];
-    const uint32_t base = H.off - TR.v0, loc = vt - base;
+    const uint32_t base = H.off - TR.v0;
     const int G = H.G, G1 = G + 1, nm = G1 * G1;
+    if (cmp) {
+        // compact tiles: the thread's entry follows from its record and the
+        // block's header (category matrix row-major, then the T_q in category
+        // order); its own value is loaded now and arrives with the first
+        // gathers, the base and extra terms after the gathers
+        vt = base + (isT ? (uint32_t)nm + (uint32_t)__popc(H.tmask & ((1u << (A - 1u)) - 1u))
+                         : A * (uint32_t)G1 + B);
+        if (active) own = load_own<HAS64, HAS32>(a, TR.v0 + vt);
+    }
+    const uint32_t loc = vt - base;
     // position of the mirrored entry (row and column exchanged) in the tile,
     // for compact tiles' off-diagonal entries
     const bool has_mirror = cmp && A != B && !isT;
@@ -593,6 +598,11 @@ __device__ __forceinline__ void process_tile(const InstParams &P, const Dev &D, 
             // all slots at once
             if (ph + 1 < NPH) asm("" : "+v"(gph) : "v"(hier.x), "v"(hier.y));
         }
+    }
+    if (cmp && active) {
+        // used last: loaded after the gathers, they arrive during the grouped sums
+        if (BASE == BASE_Y) ybv = (a.policy & 2u) ? ld_stream(a.ybase + TR.v0 + vt) : a.ybase[TR.v0 + vt];
+        if (EXTRA) ex = a.extra[TR.v0 + vt];
     }
     double *md = S.md + (H.cat_base - TR.c0);
     if (active && loc - 1u < (uint32_t)G) {   // one thread per category of the block
@@ -1681,8 +1691,7 @@ int heom_table_info(const heom_tables *h, heom_sizes *out) {
     out->compact = t.compact ? 1 : 0;
     size_t covered = 0;
     for (const TileRec &r : t.tiles) covered += r.nv;
-    out->stage_table_bytes = (int64_t)t.image.size() -
-                             (t.compact ? (int64_t)((sizeof(VarRec) + sizeof(uint16_t)) * (t.n_var - covered)) : 0);
+    out->stage_table_bytes = (int64_t)t.image.size() - (t.compact ? (int64_t)(sizeof(VarRec) * (t.n_var - covered)) : 0);
     out->own_entries = t.own_entries;
     out->read_entries = t.read_entries;
     return HEOM_OK;

@@ -77,8 +77,8 @@ HEOM_HD int conn_remap(uint32_t info, int q, int r) {
 // their variables, categories and hierarchy gather indices. 32 bytes.
 // With compact tiles (Hermitian ADOs) the tile's threads cover only the
 // entries of the upper triangle (row <= column) and the T_q of its blocks:
-// nv counts those, and the decode record and variable index of thread t are
-// at v0 + t of the records and of the compact index list.
+// nv counts those, and the decode record of thread t is at v0 + t of the
+// records (its entry follows from the record and the block's header).
 struct TileRec {
     uint32_t p0, np;     // patterns
     uint32_t v0, nv;     // unique variables (compact: the covered entries)
@@ -139,7 +139,7 @@ struct InstParams {
     uint32_t compact;  // 1: compact tiles (see TileRec)
     uint32_t tcol;     // 1: column moves name transposed positions
     // byte offsets of the sections from the image base
-    uint64_t off_lut, off_hdr, off_cat, off_gidx, off_tile, off_vrec, off_vloc;
+    uint64_t off_lut, off_hdr, off_cat, off_gidx, off_tile, off_vrec, off_end;
 };
 
 struct HostTables {
@@ -158,7 +158,8 @@ struct HostTables {
     std::vector<TileRec> tiles;         // workgroup tiles
     std::vector<uint32_t> gidx;         // per-tile lists of gather target indices
     std::vector<VarRec> vrec;           // per-variable decode records
-    std::vector<uint16_t> vloc;         // compact tiles: tile-relative variable of each thread
+    std::vector<uint16_t> vloc;         // compact tiles: tile-relative variable of each thread (host
+                                        // only: the element counts and the tile checker; not in the image)
     uint32_t max_np = 0, max_nc = 0, max_ng = 0, lds_bytes = 0, val_len = 0;
     uint32_t lds_low = 0, lds_top = 0;      // LDS of a launch over the tiles below / in the top tier
     uint32_t lds_persist = 0;               // LDS of the persistent kernel (lists kept for every stage)

@@ -697,13 +697,12 @@ static InstParams make_params(const HostTables &num, const HostTables &st) {
     ip.off_gidx = o;  o = align256(o + st.gidx.size() * sizeof(uint32_t));
     ip.off_tile = o;  o = align256(o + st.tiles.size() * sizeof(TileRec));
     ip.off_vrec = o;  o = align256(o + st.vrec.size() * sizeof(VarRec));
-    ip.off_vloc = o;
+    ip.off_end = o;
     return ip;
 }
 
 size_t image_bytes(const HostTables &t) {
-    const InstParams ip = make_params(t, t);
-    return align256(ip.off_vloc + t.vloc.size() * sizeof(uint16_t));
+    return make_params(t, t).off_end;
 }
 
 // Copy a section into the image (an empty section copies nothing: memcpy
@@ -746,7 +745,6 @@ void pack_image(HostTables *t) {
     put_section(&t->image, ip.off_gidx, t->gidx);
     put_section(&t->image, ip.off_tile, t->tiles);
     put_section(&t->image, ip.off_vrec, t->vrec);
-    put_section(&t->image, ip.off_vloc, t->vloc);
 }
 
 }  // namespace heom

@@ -2,7 +2,8 @@
 // plain, transposed-target and compact tiles: every tile's ranges, decode
 // records and gather indices stay in bounds; with compact tiles every
 // variable of a tile is either a covered entry (row <= column, or a T_q) or
-// the mirror of exactly one covered entry; with transposed targets a column
+// the mirror of exactly one covered entry, found from its decode record and
+// its block's header alone; with transposed targets a column
 // move names the mirrored position of the entry a plain table names; every
 // tile's metadata fits the LDS its launch allocates.
 // Prints "ok" and exits 0, or names the first failure and exits 1.
@@ -109,6 +110,12 @@ static int check(int64_t N, int m, int L, int d, int tv) {
             const Entry &e = E[v];
             if (e.p != R.p0 + pi || e.A != A || e.B != B || e.T != isT) return fail("decode record", v, th);
             if (A > B) return fail("lower-triangle thread", v, th);
+            // the kernels find the entry from the record and the block header alone
+            const PatHdr &H = comp.hdr[R.p0 + pi];
+            const uint32_t G1 = H.G + 1u;
+            const uint32_t derived = H.off + (isT ? G1 * G1 + (uint32_t)__builtin_popcount(H.tmask & ((1u << (A - 1u)) - 1u))
+                                                  : A * G1 + B);
+            if (derived != v) return fail("entry from record and header", v, derived);
             cover[v]++;
             if (A != B && !isT) cover[mirror(v)]++;
             const uint32_t goff = vr.x >> 18, nl = (uint32_t)__builtin_popcount(vr.y);

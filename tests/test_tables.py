@@ -179,7 +179,7 @@ def test_transposed_copies_sizes_and_knob():
 
 def test_compact_tiles_sizes_and_knob():
     """Compact tiles: transposed column targets without copies (work stays
-    32 bytes per variable), plus a 2-byte variable index per variable."""
+    32 bytes per variable); each thread's entry follows from its decode record."""
     p = W.random_problem(6, 3, 3, 1, seed=4)
     T = heom.Tables(p)
     i0 = T.info()
