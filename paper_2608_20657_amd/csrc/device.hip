@@ -80,6 +80,7 @@ struct heom_batch {
         int32_t slot;     // >= 0: tiles tile0.. of this slot alone (batch_stage_single)
         uint32_t tile0;
         bool shared = false;   // tiles of structures shared by several slots (batch_stage_shared)
+        bool compact = false;  // every slot of the group has compact tiles (kernels specialised for them)
     };
     std::vector<SlotRec> recs;        // host copy of the committed slot records
     std::vector<Group> groups;
@@ -1007,18 +1008,21 @@ __device__ __forceinline__ BatchCtx batch_ctx(const SlotRec &rec, uint32_t tile,
 
 // The stage pattern SV of one tile (FP64: 0 = first stage, 1 = the others;
 // FP32: 0 = first, 1 = second and third, 2 = last).
-template <int M, int PREC, bool TOP, int SV>
+// CM: 2 = the tile kind read from each slot's parameter block, 1 = every
+// slot of the launch has compact tiles (the registers of the compact-only
+// code, as in stage_kernel).
+template <int M, int PREC, bool TOP, int SV, int CM = 2>
 __device__ __forceinline__ void batch_tile(const BatchCtx &c, unsigned char *smem, int stage = STAGE_ALL) {
     const InstParams &P = *c.D.ip;
     const Smem S = carve(smem, P, true);
     const uint32_t lw = lut_words(P);
     if (PREC == HEOM_FP64) {
-        if (SV == 0) process_tile<M, true, false, BASE_IN, false, true, TOP, 2>(P, c.D, c.TR, S, c.a, c.first, stage, lw);
-        else process_tile<M, true, false, BASE_Y, false, true, TOP, 2>(P, c.D, c.TR, S, c.a, c.first, stage, lw);
+        if (SV == 0) process_tile<M, true, false, BASE_IN, false, true, TOP, CM>(P, c.D, c.TR, S, c.a, c.first, stage, lw);
+        else process_tile<M, true, false, BASE_Y, false, true, TOP, CM>(P, c.D, c.TR, S, c.a, c.first, stage, lw);
     } else {
-        if (SV == 0) process_tile<M, true, false, BASE_NONE, false, false, TOP, 2>(P, c.D, c.TR, S, c.a, false, stage, lw);
-        else if (SV == 1) process_tile<M, false, true, BASE_NONE, true, false, TOP, 2>(P, c.D, c.TR, S, c.a, false, stage, lw);
-        else process_tile<M, false, true, BASE_Y, true, true, TOP, 2>(P, c.D, c.TR, S, c.a, c.first, stage, lw);
+        if (SV == 0) process_tile<M, true, false, BASE_NONE, false, false, TOP, CM>(P, c.D, c.TR, S, c.a, false, stage, lw);
+        else if (SV == 1) process_tile<M, false, true, BASE_NONE, true, false, TOP, CM>(P, c.D, c.TR, S, c.a, false, stage, lw);
+        else process_tile<M, false, true, BASE_Y, true, true, TOP, CM>(P, c.D, c.TR, S, c.a, c.first, stage, lw);
     }
 }
 
@@ -1035,25 +1039,25 @@ __device__ __forceinline__ void advance_counter(int64_t *ctr, uint32_t advance) 
 // arithmetic as in stage_kernel, so a problem's trajectory does not depend
 // on the other problems in the batch. SV is a template parameter, so each
 // instance holds only the registers of its own stage pattern.
-template <int M, int PREC, bool TOP, int SV>
+template <int M, int PREC, bool TOP, int SV, int CM>
 __global__ __launch_bounds__(MAX_TILE) void batch_stage_kernel(const SlotRec *slots, const BatchTile *btiles, int s,
                                                              int64_t *ctr, uint32_t policy, uint32_t advance) {
     extern __shared__ __align__(16) unsigned char smem[];
     const BatchTile B = btiles[blockIdx.x];
     const BatchCtx c = batch_ctx<PREC>(slots[B.slot], B.tile & ~BTILE_TOP, s, ctr, policy);
-    batch_tile<M, PREC, TOP, SV>(c, smem);
+    batch_tile<M, PREC, TOP, SV, CM>(c, smem);
     advance_counter(ctr, advance);
 }
 
 // The tiles tile0.. of one slot, whose record comes in the kernel arguments
 // (as a state's tables do for stage_kernel): no list or record lookups
 // before the first loads. For slots large enough to fill launches alone.
-template <int M, int PREC, bool TOP, int SV>
+template <int M, int PREC, bool TOP, int SV, int CM>
 __global__ __launch_bounds__(MAX_TILE) void batch_stage_single(SlotRec R, uint32_t tile0, int s, int64_t *ctr,
                                                              uint32_t policy, uint32_t advance) {
     extern __shared__ __align__(16) unsigned char smem[];
     const BatchCtx c = batch_ctx<PREC>(R, tile0 + blockIdx.x, s, ctr, policy);
-    batch_tile<M, PREC, TOP, SV>(c, smem);
+    batch_tile<M, PREC, TOP, SV, CM>(c, smem);
     advance_counter(ctr, advance);
 }
 
@@ -1353,6 +1357,37 @@ int check_dev(const void *p, const char *name) {
     return HEOM_OK;
 }
 
+// One-slot-per-workgroup launch of a group: the group's only slot
+// (batch_stage_single) or its tile list (batch_stage_kernel).
+template <int M, int PREC, bool TOP, int CM>
+void batch_launch_plain(const heom_batch *b, const heom_batch::Group &g, hipStream_t s, const SlotRec *recs,
+                        const BatchTile *first, int stage, int sv, int64_t *ctr, uint32_t policy, uint32_t advance) {
+    const dim3 grid(g.count), block(g.block);
+    if (g.slot >= 0) {
+        const SlotRec &R = b->recs[(size_t)g.slot];
+        const uint32_t tile0 = g.tile0;
+        if (sv == 0)
+            hipLaunchKernelGGL((batch_stage_single<M, PREC, TOP, 0, CM>), grid, block, g.lds, s, R, tile0, stage, ctr,
+                               policy, advance);
+        else if (sv == 1)
+            hipLaunchKernelGGL((batch_stage_single<M, PREC, TOP, 1, CM>), grid, block, g.lds, s, R, tile0, stage, ctr,
+                               policy, advance);
+        else if (PREC == HEOM_FP32)
+            hipLaunchKernelGGL((batch_stage_single<M, PREC, TOP, 2, CM>), grid, block, g.lds, s, R, tile0, stage, ctr,
+                               policy, advance);
+        return;
+    }
+    if (sv == 0)
+        hipLaunchKernelGGL((batch_stage_kernel<M, PREC, TOP, 0, CM>), grid, block, g.lds, s, recs, first, stage, ctr,
+                           policy, advance);
+    else if (sv == 1)
+        hipLaunchKernelGGL((batch_stage_kernel<M, PREC, TOP, 1, CM>), grid, block, g.lds, s, recs, first, stage, ctr,
+                           policy, advance);
+    else if (PREC == HEOM_FP32)
+        hipLaunchKernelGGL((batch_stage_kernel<M, PREC, TOP, 2, CM>), grid, block, g.lds, s, recs, first, stage, ctr,
+                           policy, advance);
+}
+
 template <int M, int PREC, bool TOP>
 void batch_launch_group(const heom_batch *b, const heom_batch::Group &g, hipStream_t s, const SlotRec *recs,
                         const BatchTile *first, int stage, int64_t *ctr, uint32_t policy, uint32_t advance) {
@@ -1372,29 +1407,8 @@ void batch_launch_group(const heom_batch *b, const heom_batch::Group &g, hipStre
                                ctr, policy, advance);
         return;
     }
-    if (g.slot >= 0) {
-        const SlotRec &R = b->recs[(size_t)g.slot];
-        const uint32_t tile0 = g.tile0;
-        if (sv == 0)
-            hipLaunchKernelGGL((batch_stage_single<M, PREC, TOP, 0>), grid, block, g.lds, s, R, tile0, stage, ctr,
-                               policy, advance);
-        else if (sv == 1)
-            hipLaunchKernelGGL((batch_stage_single<M, PREC, TOP, 1>), grid, block, g.lds, s, R, tile0, stage, ctr,
-                               policy, advance);
-        else if (PREC == HEOM_FP32)
-            hipLaunchKernelGGL((batch_stage_single<M, PREC, TOP, 2>), grid, block, g.lds, s, R, tile0, stage, ctr,
-                               policy, advance);
-        return;
-    }
-    if (sv == 0)
-        hipLaunchKernelGGL((batch_stage_kernel<M, PREC, TOP, 0>), grid, block, g.lds, s, recs, first, stage, ctr,
-                           policy, advance);
-    else if (sv == 1)
-        hipLaunchKernelGGL((batch_stage_kernel<M, PREC, TOP, 1>), grid, block, g.lds, s, recs, first, stage, ctr,
-                           policy, advance);
-    else if (PREC == HEOM_FP32)
-        hipLaunchKernelGGL((batch_stage_kernel<M, PREC, TOP, 2>), grid, block, g.lds, s, recs, first, stage, ctr,
-                           policy, advance);
+    if (g.compact) batch_launch_plain<M, PREC, TOP, 1>(b, g, s, recs, first, stage, sv, ctr, policy, advance);
+    else batch_launch_plain<M, PREC, TOP, 2>(b, g, s, recs, first, stage, sv, ctr, policy, advance);
 }
 
 
@@ -2182,6 +2196,7 @@ int heom_batch_commit(heom_batch *b, void *dev, size_t bytes, void *stream) {
         for (int tv : sizes)
             for (int top = 0; top < 2; ++top) {
                 Pending P{{m, top != 0, (uint32_t)tv, 0u, 0u, 0u, -1, 0u}, {}, {}};
+                bool all_compact = true;
                 for (size_t i = 0; i < ns; ++i) {
                     const BatchSlotHost &S = b->slots[i];
                     if (!S.used || S.tables->t.m != m || S.tables->t.tile_vars != tv) continue;
@@ -2200,7 +2215,9 @@ int heom_batch_commit(heom_batch *b, void *dev, size_t bytes, void *stream) {
                     // (the top tier's lists are about a third as long)
                     const uint32_t lds = split < T ? (top ? t.lds_top : t.lds_low) : t.lds_bytes;
                     P.g.lds = std::max<uint32_t>(P.g.lds, lds);
+                    all_compact = all_compact && t.compact;
                 }
+                P.g.compact = all_compact;
                 if (!P.tiles.empty()) pend.push_back(std::move(P));
             }
     std::vector<size_t> order(pend.size());
