@@ -1,0 +1,95 @@
+"""The batched draw at full size, in the launch configuration the benchmark
+times: the 512 problems of seed 0 (533.8 M unique variables), compact tiles
+under HEOM_HERMITIAN, one image per structure key with a parameter block per
+problem, one heom_batch_propagate for all of them (default merge threshold
+and launch shapes).
+
+Sampled outputs: the four smallest problems of the draw and four more of
+at most 40,000 variables are propagated by the oracle (its generator M_u and
+classical RK4) and compared entry by entry;
+the largest one (17.3 M variables, its own top-tier launches) and a few
+others drawn at random are compared bitwise with heom_propagate run alone
+on the same parameters, which the other GPU tests compare with the oracle
+(element by element and, at 17.3 M variables, on sampled rows).
+"""
+import numpy as np
+import pytest
+
+from oracle import integrate, uvar
+from paper_2608_20657_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+DT, STEPS = 0.02, 3
+
+
+def structure_key(q):
+    return (min(q.N, q.L + q.d + 2), q.m, q.L, q.d)
+
+
+def test_batched_draw_full_size():
+    from tests.gpu_util import torch_cuda
+    torch_cuda()
+    import torch
+    from paper_2608_20657_amd import heom
+    flag = heom.HEOM_FP64 | heom.HEOM_HERMITIAN
+    st = torch.cuda.current_stream()
+    ps = W.draw_batch(512, 0)
+    structs, imgs = {}, {}
+    for q in ps:
+        k = structure_key(q)
+        if k not in structs:
+            T = heom.Tables(q)
+            T.set_tuning(compact=1)
+            structs[k] = T
+            imgs[k] = torch.empty(T.info()["table_bytes"], dtype=torch.uint8, device="cuda")
+            T.upload(imgs[k], st)
+    inst = []
+    batch = heom.Batch(len(ps))
+    for i, q in enumerate(ps):
+        T = structs[structure_key(q)]
+        info = T.info()
+        params = torch.empty(T.params_bytes(), dtype=torch.uint8, device="cuda")
+        T.upload_params(q, params, st)
+        y = torch.empty(info["n_var"], dtype=torch.complex128, device="cuda")
+        t0 = T.tier0_pure(1.0, 0.0, [0.0] * q.d)
+        T.init_state(t0, y, st)
+        work = torch.empty(info["work_bytes_fp64"], dtype=torch.uint8, device="cuda")
+        batch.set_slot(i, T, y, work, DT, params=params)
+        inst.append((q, T, y, t0, info["n_var"]))
+    assert sum(x[4] for x in inst) == 533842589
+    batch.commit(torch, st)
+    batch.propagate(STEPS, flag, st)
+    torch.cuda.synchronize()
+    assert int(batch.status(st).sum()) == 0
+
+    # the four smallest problems and four more of at most 40,000 variables
+    # against the oracle, entry by entry
+    order = sorted(range(len(inst)), key=lambda i: inst[i][4])
+    rng = np.random.default_rng(0)
+    mid = [i for i in order[4:] if inst[i][4] <= 40000]
+    for i in order[:4] + [int(v) for v in rng.choice(mid, 4, replace=False)]:
+        q, T, y, t0, nv = inst[i]
+        S = uvar.UVarSystem(q)
+        assert S.n_var == nv
+        y0 = np.zeros(nv, dtype=np.complex128)
+        y0[:t0.size] = t0
+        ref, _ = integrate.propagate(S.generator(), y0, DT, STEPS)
+        got = y.cpu().numpy()
+        assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max(), (i, nv)
+
+    # the largest problem and a random sample against the single-problem path, bitwise
+    rng = np.random.default_rng(1)
+    picks = [order[-1]] + [int(v) for v in rng.choice(len(inst), 4, replace=False)]
+    for i in picks:
+        q, T, y, t0, nv = inst[i]
+        k = structure_key(q)
+        T.set_params(q)
+        T.upload(imgs[k], st)
+        ys = torch.empty(nv, dtype=torch.complex128, device="cuda")
+        T.init_state(t0, ys, st)
+        work = torch.empty(T.info()["work_bytes_fp64"], dtype=torch.uint8, device="cuda")
+        T.propagate(ys, work, DT, STEPS, 0, None, flag, st)
+        torch.cuda.synchronize()
+        assert torch.equal(ys, y), (i, nv)
+        del ys, work
