@@ -49,6 +49,7 @@ import json
 import math
 import os
 import sys
+import tempfile
 import time
 
 import numpy as np
@@ -143,6 +144,19 @@ def time_propagate(T, torch, tier0, dt, steps, warmup, obs_every, precision):
     return ms, wall, y, obs
 
 
+_TIMER_DIR = None
+
+
+def cpu_timer_exe():
+    """The CPU baseline's RK4 loop compiled for this host (-march=native),
+    in a temporary directory removed when the process ends."""
+    global _TIMER_DIR
+    from oracle import cpu_timer
+    if _TIMER_DIR is None:
+        _TIMER_DIR = tempfile.TemporaryDirectory(prefix="heom_cpu_timer_")
+    return cpu_timer.build_timer(_TIMER_DIR.name)
+
+
 def cpu_baseline(dt, var_budget, max_vars, steps=2000, local_steps=10000):
     """The oracle's generator M_u (oracle.uvar) run by the compiled classical
     RK4 loop (oracle/csr_rk4.c, OpenMP) on the host cores: a bounded sample
@@ -154,7 +168,7 @@ def cpu_baseline(dt, var_budget, max_vars, steps=2000, local_steps=10000):
     (unique-variable RHS updates/s, four per RK4 step)."""
     from oracle import cpu_timer, uvar
     from paper_2608_20657_amd import workloads as W
-    exe = cpu_timer.build_timer(os.path.join(ROOT, "gpurun_out", "cpu_timer"))
+    exe = cpu_timer_exe()
     threads = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
     picked, total = [], 0
     t0 = time.perf_counter()
@@ -201,7 +215,7 @@ def cpu_configs(dt_small=0.05, dt=0.02):
     (the saturated workload over a 500-step prefix)."""
     from oracle import cpu_timer, uvar
     from paper_2608_20657_amd import workloads as W
-    exe = cpu_timer.build_timer(os.path.join(ROOT, "gpurun_out", "cpu_timer"))
+    exe = cpu_timer_exe()
     threads = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
     out = {}
     for name, p, h, steps, one_steps, amp in (
