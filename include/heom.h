@@ -188,8 +188,9 @@ int heom_tier0_expand(const heom_tables *t, const double *tier0, double *R);
  * bytes (row and column sums of rho0's molecule block, totals), overwritten.
  * out_dev: device, (N+1)x(N+1) complex doubles, overwritten; may not alias
  * rho0_dev or work_dev. Stream-ordered on `stream`, nothing allocated.
- * Errors: HEOM_E_INVAL (N out of range, NULL pointer, unknown mask bits,
- * the adjoint flag without bit 2), HEOM_E_TOO_LARGE (work too small). */
+ * Errors: HEOM_E_INVAL (N out of range, NULL pointer, a device buffer not
+ * 16-byte aligned, unknown mask bits, the adjoint flag without bit 2),
+ * HEOM_E_TOO_LARGE (work too small). */
 #define HEOM_RECON_MAX_N 4096
 #define HEOM_RECON_R_DOUBLES 164
 #define HEOM_RECON_CE_ADJOINT 32u

@@ -192,6 +192,9 @@ int heom_reconstruct_dense(int64_t N, const void *rho0_dev, const double *R, uin
                            size_t work_bytes, void *out_dev, void *stream) {
     if (N < 1 || N > HEOM_RECON_MAX_N) return heom::set_error(HEOM_E_INVAL, "N out of range for the dense output");
     if (!rho0_dev || !R || !work_dev || !out_dev) return heom::set_error(HEOM_E_INVAL, "NULL pointer");
+    if ((reinterpret_cast<uintptr_t>(rho0_dev) | reinterpret_cast<uintptr_t>(work_dev) |
+         reinterpret_cast<uintptr_t>(out_dev)) % 16)
+        return heom::set_error(HEOM_E_INVAL, "device buffers must be 16-byte aligned");
     if (mask & ~(0x1fu | HEOM_RECON_CE_ADJOINT)) return heom::set_error(HEOM_E_INVAL, "unknown mask bits");
     if ((mask & HEOM_RECON_CE_ADJOINT) && (mask & 4u) == 0)
         return heom::set_error(HEOM_E_INVAL, "the adjoint form is for the |c><e_1| type");

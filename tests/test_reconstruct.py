@@ -154,6 +154,8 @@ def test_reconstruct_dense_argument_errors():
     assert lib.heom_reconstruct_dense(5, dummy, dp, 64, dummy, 1 << 20, dummy, None) == -1       # unknown bit
     assert lib.heom_reconstruct_dense(5, dummy, dp, 2 | 32, dummy, 1 << 20, dummy, None) == -1   # adjoint without ce
     assert lib.heom_reconstruct_dense(5, dummy, dp, 1, dummy, 16 * 13, dummy, None) == -3        # work too small
+    odd = ctypes.c_void_p(24)
+    assert lib.heom_reconstruct_dense(5, odd, dp, 1, dummy, 1 << 20, dummy, None) == -1         # misaligned
 
 
 def random_slots(rng, scale=1.0):
