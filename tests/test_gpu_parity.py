@@ -53,6 +53,22 @@ def test_rhs_structures(N, m, L, d):
     check_rhs(p, seed=N)
 
 
+@pytest.mark.parametrize("N,m,L,d", [(3, 1, 63, 0), (2, 2, 20, 0), (16, 1, 2, 15)])
+def test_rhs_limits(N, m, L, d):
+    """The deepest hierarchy the library takes (L = HEOM_MAX_L = 63: 124,146
+    variables, occupations up to 63 in the coefficient tables and category
+    vectors), a deep two-channel one, and patterns with the most categories
+    it takes (G = HEOM_MAX_G = 16: fifteen distinguished molecules and the
+    pool), every entry against the oracle."""
+    p = W.random_problem(N, m, L, d, seed=5, complex_check=True, terminator=True)
+    T, _ = check_rhs(p, seed=N + L)
+    info = T.info()
+    if L == 63:
+        assert info["n_var"] == 124146
+    if d == 15:
+        assert info["max_G"] == 16
+
+
 def test_rhs_switched_off_and_static_channels():
     p = W.random_problem(5, 3, 4, 1, seed=11)
     p.c[1] = 0j

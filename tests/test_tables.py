@@ -22,7 +22,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 STRUCTS = [(2, 1, 3, 0), (4, 2, 3, 0), (4, 2, 3, 1), (3, 2, 4, 1), (5, 1, 3, 1), (4, 1, 4, 2),
            (3, 3, 2, 1), (1, 2, 3, 0), (2, 1, 0, 0), (3, 1, 2, 3), (6, 4, 3, 0), (12, 1, 10, 0),
-           (7, 2, 5, 2), (30, 8, 2, 0)]
+           (7, 2, 5, 2), (30, 8, 2, 0), (3, 1, 63, 0), (16, 1, 2, 15)]
 
 
 def test_exports_every_header_symbol():
