@@ -71,6 +71,25 @@ def test_rhs_hermitian_small_vs_oracle(N, m, L, d, tuning):
     assert np.all(np.abs(got32 - want) <= fp32_bound(A, y32, want))
 
 
+@pytest.mark.parametrize("N,m,L,d,tv", [(3, 1, 63, 0, 64), (16, 1, 2, 15, 512)])
+def test_rhs_hermitian_compact_limits(N, m, L, d, tv):
+    """Compact tiles at the library's limits (L = 63 with 64-variable tiles:
+    1,321 tiles; 16 categories per pattern, whose 289-entry blocks need
+    512-variable tiles), every element in FP64 and FP32 against the oracle
+    on a Hermitian state."""
+    p = W.random_problem(N, m, L, d, seed=7 * N + L, complex_check=False, loss=True, terminator=True)
+    T, torch = tables(p, compact=1, tile_vars=tv)
+    S = uvar.UVarSystem(p)
+    A = S.generator()
+    y = hermitian_vector(S, seed=L + d)
+    got = gpu_rhs_prec(T, torch, y, HERM)
+    assert np.all(np.abs(got - A @ y) <= rhs_bound(A, y))
+    y32 = y.astype(np.complex64).astype(np.complex128)
+    got32 = gpu_rhs_prec(T, torch, y32, HERM | 1).astype(np.complex128)
+    want = A @ y32
+    assert np.all(np.abs(got32 - want) <= fp32_bound(A, y32, want))
+
+
 @pytest.mark.parametrize("N,m,L,tv", [(100, 4, 7, 128), (100, 3, 8, 64)])
 def test_rhs_split_top_tier_every_element(N, m, L, tv):
     """States with >= 2048 tiles, where each stage is a lower-tier launch
