@@ -506,6 +506,31 @@ def localized_section(torch, args, precision, herm):
     }
 
 
+def time_rhs(T, torch, y, precision, info, calls=20):
+    """heom_rhs alone (dy = M_u y, no RK4 combination) on a resident state:
+    mean time per call from HIP events over `calls` calls, in unique-variable
+    RHS updates/s and against the HBM peak (reads y, writes dy: 32 B per
+    variable, plus the tables)."""
+    s = torch.cuda.current_stream()
+    dy = torch.empty_like(y)
+    for _ in range(3):
+        T.rhs(y, dy, s, precision=precision)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for _ in range(calls):
+        T.rhs(y, dy, s, precision=precision)
+    e1.record(s)
+    torch.cuda.synchronize()
+    us = e0.elapsed_time(e1) * 1e3 / calls
+    nbytes = 32 * info["n_var"] + info["stage_table_bytes"]
+    gbs = nbytes / (us * 1e-6) / 1e9
+    del dy
+    return {"mean_us": round(us, 2), "rhs_updates_per_s": info["n_var"] / (us * 1e-6),
+            "algorithmic_bytes_per_call": int(nbytes), "achieved_GBps": round(gbs, 1),
+            "frac": round(gbs / HBM_PEAK_GBS, 4), "calls": calls}
+
+
 def probe_section(torch, args, herm, general=True):
     """The RK4 stage kernel alone on the largest structure of the draw
     (N=10^4, m=4, L=10: 17.3 M variables): mean stage time from HIP events
@@ -546,6 +571,7 @@ def probe_section(torch, args, herm, general=True):
         "rhs_updates_per_s": ri["n_var"] * 4 * args.roofline_steps / (rms / 1e3),
         "table_build_s": round(build_s, 2),
     }
+    out["heom_rhs"] = time_rhs(TR, torch, ry, herm, ri)
     del ry, img2, TR
     if herm and general:
         # the same stage on the general path (no Hermitian assertion: full
