@@ -150,10 +150,15 @@ def config_paper_static(N: int, d: int = 0) -> Problem:
 
 
 def _matsubara_pole_too_close(gam: float, m: int, kT: float) -> bool:
-    for k in range(1, m):
+    """gamma within 5% of a Matsubara rate nu_k = 2 pi k kT (k >= 1): there
+    cot(gamma / 2kT) in the Debye coefficient diverges, whatever m, and so
+    does the Matsubara coefficient c_k if the bath keeps that term."""
+    k = 1
+    while 2.0 * math.pi * k * kT <= gam / 0.95:
         vk = 2.0 * math.pi * k * kT
         if abs(gam / vk - 1.0) < 0.05:
             return True
+        k += 1
     return False
 
 
@@ -161,8 +166,9 @@ def draw_batch(n: int = 512, seed: int = 0,
                with_horizon: bool = False) -> List[Problem]:
     """Seeded ragged batch: N~U{4..5000}, m~U{1..4}, L~U{3..10},
     g~U[0.002,0.03], lam~U[0.005,0.05], gam~U[0.02,0.2], kappa~U[0,0.02],
-    kT=0.025, resonant, d=0. A gamma within 5% of a Matsubara rate (where
-    the k>=1 coefficient diverges) is redrawn. With with_horizon, each
+    kT=0.025, resonant, d=0. A gamma within 5% of a Matsubara rate 2 pi k kT
+    (k >= 1; there the Debye coefficient's cot and the k-th Matsubara
+    coefficient diverge) is redrawn, whatever m. With with_horizon, each
     problem carries a step count U{1000..20000} as attribute `horizon`."""
     rng = np.random.default_rng(seed)
     out = []
