@@ -308,7 +308,7 @@ def batched_section(torch, steps, warmup, n=512, seed=0, dt=0.02, flag=0, compac
     if tune_shape:
         from paper_2608_20657_amd import autotune
         shape = autotune.autotune_batch(batch, torch, steps=3, precision=flag, merges=(0, 4096, 16384, 65536),
-                                        shares=(1, 2))
+                                        shares=(1, 2), interleaves=(0, 8, 32, 128))
     out = {"workload": f"{n} independent problems drawn with seed {seed}: N~U{{4..5000}}, m~U{{1..4}}, "
                        "L~U{3..10}, g~U[0.002,0.03], lam~U[0.005,0.05], gam~U[0.02,0.2], kappa~U[0,0.02], "
                        "kT=0.025, resonant, d=0, rho(0)=|c><c|, dt=0.02",
@@ -320,7 +320,8 @@ def batched_section(torch, steps, warmup, n=512, seed=0, dt=0.02, flag=0, compac
            "element_bytes_per_step": elem,
            "tuned_tile_vars": tiles or None,
            "tuned_launch_shape": ({"best": shape["best"], "ms_per_step": {f"merge={c['merge_tiles']},share="
-                                   f"{c['share_slots']}": round(t, 3) for c, t in shape["results"]}}
+                                   f"{c['share_slots']},interleave={c['interleave']}": round(t, 3)
+                                   for c, t in shape["results"]}}
                                   if shape else None)}
     for prec, name in ((0, "fp64_batched"), (1, "fp32_batched")):
         for q, T, params, y, work, t0v, _ in inst:

@@ -460,6 +460,16 @@ int heom_batch_set_graph(heom_batch *b, int32_t steps);
  * heom_batch_commit (required). */
 int heom_batch_set_merge(heom_batch *b, int32_t max_tiles);
 
+/* Launch shape: the order of the tiles in the groups that run one workgroup
+ * per slot and tile. 0: slot by slot. tiles > 0: the slots that use the same
+ * uploaded structure take turns, `tiles` consecutive tiles each, so that
+ * workgroups resident together read the same connection tables (beyond
+ * saturation problems of one structure key share them, Sec. V.C.4) and one
+ * fetch of them serves several problems. Default 32. Results are bitwise the
+ * same either way. Takes effect at the next heom_batch_commit (required). Errors: E_INVAL
+ * if tiles < 0. */
+int heom_batch_set_interleave(heom_batch *b, int32_t tiles);
+
 /* Wait for `stream` and report whether any occupied slot's tier-0 block
  * became NaN or infinite during a heom_batch_propagate since the last
  * heom_batch_commit (which clears the flags): HEOM_E_NONFINITE if so, else

@@ -67,11 +67,12 @@ def autotune(T: "heom.Tables", torch, tier0, dt: float, steps: int = 40, precisi
 
 
 def autotune_batch(batch: "heom.Batch", torch, steps: int = 3, precision: int = heom.HEOM_FP64,
-                   merges=(0, 4096, 16384, 65536), shares=(1, 2), repeats: int = 1,
+                   merges=(0, 4096, 16384, 65536), shares=(1, 2), interleaves=(32,), repeats: int = 1,
                    verbose: bool = False) -> Dict:
     """Pick the launch shape of a batch: the merge threshold of its small
-    groups (heom_batch_set_merge) and the slots per shared workgroup
-    (heom_batch_set_share). Times `steps` RK4 steps of every slot for each
+    groups (heom_batch_set_merge), the slots per shared workgroup
+    (heom_batch_set_share) and the chunk in which slots of one structure take
+    turns (heom_batch_set_interleave). Times `steps` RK4 steps of every slot for each
     combination with HIP events on the launch stream and keeps the fastest.
     Every shape gives bitwise the same results; tuning advances the states,
     so each slot's state is saved before and restored after, and every slot
@@ -81,9 +82,10 @@ def autotune_batch(batch: "heom.Batch", torch, steps: int = 3, precision: int = 
     saved = {k: (v, v[2].clone()) for k, v in batch._keep.items()}
     dts = dict(batch._dt)
     results = []
-    for mg, sh in itertools.product(merges, shares):
+    for mg, sh, il in itertools.product(merges, shares, interleaves):
         batch.set_merge(mg)
         batch.set_share(sh)
+        batch.set_interleave(il)
         batch.commit(torch, s)
         best = float("inf")
         for r in range(repeats + 1):
@@ -94,12 +96,13 @@ def autotune_batch(batch: "heom.Batch", torch, steps: int = 3, precision: int = 
             torch.cuda.synchronize()
             if r > 0:                       # the first run warms up
                 best = min(best, e0.elapsed_time(e1) / steps)
-        results.append((dict(merge_tiles=mg, share_slots=sh), best))
+        results.append((dict(merge_tiles=mg, share_slots=sh, interleave=il), best))
         if verbose:
-            print(f"autotune_batch merge={mg} share={sh}: {best:.3f} ms/step", flush=True)
+            print(f"autotune_batch merge={mg} share={sh} interleave={il}: {best:.3f} ms/step", flush=True)
     cbest, tbest = min(results, key=lambda x: x[1])
     batch.set_merge(cbest["merge_tiles"])
     batch.set_share(cbest["share_slots"])
+    batch.set_interleave(cbest["interleave"])
     for slot, ((tables, params, y, work, obs, every), y0) in saved.items():
         y.copy_(y0)
         batch.set_slot(slot, tables, y, work, dts[slot], params=params, obs=obs, obs_every=every)

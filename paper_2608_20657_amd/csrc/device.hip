@@ -93,6 +93,10 @@ struct heom_batch {
     // side in one workgroup per tile (batch_stage_pair), 1 = every slot has
     // its own workgroups.
     int32_t share_slots = 1;
+    // Slots that share one structure image, in the groups with one
+    // workgroup per slot and tile: 0 = slot by slot, c > 0 = chunks of c
+    // consecutive tiles taken from each such slot in turn.
+    int32_t interleave = 32;
     size_t list_off = 0;                // slot lists of the shared groups in the batch buffer
     hipGraphExec_t gexec = nullptr;
     int gprec = -1;
@@ -2170,7 +2174,9 @@ int heom_batch_commit(heom_batch *b, void *dev, size_t bytes, void *stream) {
         R.dt = S.dt;
     }
     // Group the tiles by (m, tile size, tier class); within a group, slot by
-    // slot in slot order and each slot's tiles in order. Then the smallest
+    // slot in slot order and each slot's tiles in order (with interleave > 0
+    // the slots of one structure image take turns, a chunk of tiles each, so
+    // that workgroups running together read the same tables). Then the smallest
     // groups with m <= MERGE_MAX_M, up to merge_tiles tiles in all, become one
     // merged launch whose tiles come first in the list. In every other group,
     // with share_slots = 2, the slots that share one structure image are
@@ -2301,12 +2307,28 @@ int heom_batch_commit(heom_batch *b, void *dev, size_t bytes, void *stream) {
         if (SG.count > 0) b->groups.push_back(SG);
         heom_batch::Group G = pend[q].g;
         G.first = (uint32_t)k;
-        for (const auto &bt : pend[q].tiles)
-            if (plain_slot[bt.slot]) tl[k++] = bt;
+        if (b->interleave > 0) {
+            // the members of one image have the same tile range (same tables)
+            const uint32_t c = (uint32_t)b->interleave;
+            for (const auto &grp : by_t) {
+                const uint32_t j0 = grp[0].j0, j1 = grp[0].j1;
+                for (uint32_t jc = j0; jc < j1; jc += c)
+                    for (const Member &mb : grp) {
+                        if (!plain_slot[mb.slot]) continue;
+                        for (uint32_t j = jc; j < std::min(jc + c, j1); ++j)
+                            tl[k++] = BatchTile{mb.slot, G.top ? (j | BTILE_TOP) : j};
+                    }
+            }
+        } else {
+            for (const auto &bt : pend[q].tiles)
+                if (plain_slot[bt.slot]) tl[k++] = bt;
+        }
         G.count = (uint32_t)(k - G.first);
         if (G.count == 0) continue;
+        bool one_slot = true;
+        for (uint32_t x = G.first; x < k; ++x) one_slot = one_slot && tl[x].slot == tl[G.first].slot;
         // a group of one slot: its record goes in the kernel arguments
-        if (tl[G.first].slot == tl[k - 1].slot) {
+        if (one_slot) {
             G.slot = (int32_t)tl[G.first].slot;
             G.tile0 = tl[G.first].tile & ~BTILE_TOP;
         }
@@ -2450,6 +2472,13 @@ int heom_batch_set_graph(heom_batch *b, int32_t steps) {
 int heom_batch_set_share(heom_batch *b, int32_t max_slots) {
     if (!b || max_slots < 1 || max_slots > 2) return fail(HEOM_E_INVAL, "bad batch, or slots per workgroup not 1 or 2");
     b->share_slots = max_slots;
+    b->committed = false;
+    return HEOM_OK;
+}
+
+int heom_batch_set_interleave(heom_batch *b, int32_t tiles) {
+    if (!b || tiles < 0) return fail(HEOM_E_INVAL, "bad batch or chunk length");
+    b->interleave = tiles;
     b->committed = false;
     return HEOM_OK;
 }

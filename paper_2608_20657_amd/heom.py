@@ -38,7 +38,7 @@ SYMBOLS = ["heom_build_tables", "heom_set_params", "heom_table_info", "heom_uplo
            "heom_set_tuning", "heom_get_tuning", "heom_work_status", "heom_params_bytes",
            "heom_upload_params", "heom_batch_create", "heom_batch_set_slot", "heom_batch_clear_slot",
            "heom_batch_device_bytes", "heom_batch_commit", "heom_batch_propagate", "heom_batch_slot_steps",
-           "heom_batch_set_graph", "heom_batch_set_merge", "heom_batch_set_share", "heom_batch_status",
+           "heom_batch_set_graph", "heom_batch_set_interleave", "heom_batch_set_merge", "heom_batch_set_share", "heom_batch_status",
            "heom_batch_free", "heom_reconstruct_dense", "heom_reconstruct_work_bytes"]
 
 
@@ -114,6 +114,7 @@ def _load():
         "heom_batch_slot_steps": [vp, ctypes.c_int32, ctypes.POINTER(i64)],
         "heom_batch_set_graph": [vp, ctypes.c_int32],
         "heom_batch_set_merge": [vp, ctypes.c_int32],
+        "heom_batch_set_interleave": [vp, ctypes.c_int32],
         "heom_batch_status": [vp, ctypes.POINTER(ctypes.c_int32), ctypes.c_int32, vp],
         "heom_batch_set_share": [vp, ctypes.c_int32],
         "heom_reconstruct_dense": [i64, vp, dp, ctypes.c_uint32, vp, ctypes.c_size_t, vp, vp],
@@ -404,6 +405,12 @@ class Batch:
         max_tiles in all) as one launch per stage (0 = one launch per group).
         Takes effect at the next commit."""
         _check(LIB.heom_batch_set_merge(self._h, int(max_tiles)))
+
+    def set_interleave(self, tiles: int):
+        """Let the slots of one structure image take turns, `tiles` tiles each,
+        in the groups with one workgroup per slot (0 = slot by slot). Takes
+        effect at the next commit."""
+        _check(LIB.heom_batch_set_interleave(self._h, int(tiles)))
 
     def status(self, stream=None) -> np.ndarray:
         """Synchronize and return one flag per slot: 1 where the slot's tier-0

@@ -314,14 +314,16 @@ def test_hermitian_flag_checked_per_slot():
     torch.cuda.synchronize()
 
 
-@pytest.mark.parametrize("share", [1, 2])
-def test_shared_structure_slots_equal_solo(share):
+@pytest.mark.parametrize("share,interleave", [(1, 0), (2, 0), (1, 3)])
+def test_shared_structure_slots_equal_solo(share, interleave):
     """Slots on one uploaded structure with their own parameter blocks
     (different N beyond saturation, couplings, loss; every other slot without
     observables), computed in pairs side by side (one tile's metadata staged
-    once for both halves of a workgroup) with an odd slot out, beside slots
-    of another structure: every slot equals its heom_propagate run bitwise,
-    FP64 and FP32 increments, plain and compact tiles."""
+    once for both halves of a workgroup) with an odd slot out, or one
+    workgroup per slot with the slots of a structure taking turns three tiles
+    at a time, beside slots of another structure: every slot equals its
+    heom_propagate run bitwise, FP64 and FP32 increments, plain and compact
+    tiles."""
     from paper_2608_20657_amd import heom
     torch = torch_cuda()
     s = torch.cuda.current_stream()
@@ -333,6 +335,7 @@ def test_shared_structure_slots_equal_solo(share):
             b = heom.Batch(8)
             b.set_merge(0)
             b.set_share(share)
+            b.set_interleave(interleave)
             keep, want = [], []
             structs = []
             for bp in base:
@@ -425,9 +428,10 @@ def test_one_slot_batch_across_calls_and_graph():
 
 
 def test_autotune_batch_restores_states_and_keeps_results():
-    """autotune_batch tries merge thresholds and shared workgroups on the
-    committed batch, then restores every slot's state and step count: the
-    batch afterwards equals the slots' solo runs bitwise."""
+    """autotune_batch tries merge thresholds, shared workgroups and slot
+    interleaving on the committed batch, then restores every slot's state
+    and step count: the batch afterwards equals the slots' solo runs
+    bitwise."""
     from paper_2608_20657_amd import autotune, heom
     torch = torch_cuda()
     s = torch.cuda.current_stream()
@@ -447,8 +451,8 @@ def test_autotune_batch_restores_states_and_keeps_results():
         b.set_slot(i, T, y, work, 0.02, obs=obs, obs_every=every)
         keep.append((T, y, obs))
     b.commit(torch, s)
-    res = autotune.autotune_batch(b, torch, steps=2, merges=(0, 64), shares=(1, 2))
-    assert len(res["results"]) == 4 and res["best"] in [c for c, _ in res["results"]]
+    res = autotune.autotune_batch(b, torch, steps=2, merges=(0, 64), shares=(1, 2), interleaves=(0, 1))
+    assert len(res["results"]) == 8 and res["best"] in [c for c, _ in res["results"]]
     b.propagate(steps, 0, s)
     torch.cuda.synchronize()
     for (T, y, obs), (wy, wo) in zip(keep, want):
