@@ -314,7 +314,7 @@ def test_hermitian_flag_checked_per_slot():
     torch.cuda.synchronize()
 
 
-@pytest.mark.parametrize("share,interleave", [(1, 0), (2, 0), (1, 3)])
+@pytest.mark.parametrize("share,interleave", [(1, 0), (2, 0), (1, 3), (2, 3)])
 def test_shared_structure_slots_equal_solo(share, interleave):
     """Slots on one uploaded structure with their own parameter blocks
     (different N beyond saturation, couplings, loss; every other slot without
