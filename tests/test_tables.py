@@ -210,3 +210,16 @@ def test_element_read_counts():
     covered = sum((b.G + 1) * (b.G + 2) // 2 + b.h for b in S.blocks)
     assert i1["own_entries"] == covered
     assert covered < i1["read_entries"] <= i1["n_var"]
+
+
+def test_batch_launch_shape_arguments():
+    # host-side checks of the batch launch-shape knobs (no device call)
+    b = heom.Batch(2)
+    for bad in (lambda: b.set_interleave(-1), lambda: b.set_merge(-1), lambda: b.set_share(3)):
+        with pytest.raises(heom.HeomError) as e:
+            bad()
+        assert e.value.code == -1
+    b.set_interleave(0)
+    b.set_interleave(32)
+    b.set_merge(0)
+    b.set_share(2)
